@@ -1,0 +1,223 @@
+"""Seeded synthetic inputs shaped like the paper's single-cell workloads.
+
+This module is the only code shared by the CPU oracle and the GPU path.  It
+draws random numbers and lays them out; it holds none of the method's
+arithmetic (no Gram matrix, no eigendecomposition, no likelihood, no
+recomposition, no top-k).
+
+Recipes (all seeded, all reproducible block by block):
+
+* ``nb_log1p`` -- a cells x genes matrix X = log1p(counts) with negative
+  binomial counts (dispersion alpha, Var = mu + alpha mu^2) whose means follow
+  log mu_ij = beta0 + 0.5 (A B^T)_ij / sqrt(rank) + M[cl(i), j] + g_j with a
+  rank-8 factor A (cells x 8), B (genes x 8) ~ N(0, 1), a per-cluster gene
+  effect M ~ N(0, 1) and gene offsets g ~ N(0, variance 0.5).  Cluster sizes
+  are equal or Zipf(1.2) with largest-remainder rounding; Zipf-sized rows are
+  shuffled by a seeded permutation.  The values are rounded to float32, which
+  is what both sides consume.
+* ``cell_factor_proxy`` -- an n x r matrix with orthonormal columns whose rows
+  carry the structure of a cell-axis factor of such data: a cluster part, the
+  shared rank-8 factor and per-cell noise directions.
+* ``spectrum_proxy`` -- a descending positive spectrum of a p x p Gram matrix
+  with a few signal spikes above a Marchenko-Pastur bulk.
+
+Each row block of ``nb_log1p`` draws from its own Philox stream keyed by
+(seed, block), so any block of rows can be regenerated alone.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "zipf_sizes",
+    "cluster_labels",
+    "nb_log1p",
+    "nb_log1p_rows",
+    "dense_to_csr",
+    "cell_factor_proxy",
+    "spectrum_proxy",
+    "config",
+    "ROW_BLOCK",
+]
+
+ROW_BLOCK = 4096
+FACTOR_RANK = 8
+ALPHA = 2.0
+
+# The workloads: sizes and generator parameters of the five configurations.
+CONFIGS = {
+    0: dict(n=2000, p=500, clusters=8, zipf=False, beta0=0.0, r_c=500, r_g=500, k=10, seed=1000),
+    1: dict(n=100_000, p=2000, clusters=20, zipf=True, beta0=0.0, r_c=50, r_g=2000, k=10, seed=2000),
+    2: dict(n=1_000_000, p=20_000, clusters=40, zipf=True, beta0=None, density=0.05,
+            r_c=100, r_g=20_000, k=10, seed=3000),
+}
+
+
+def config(i: int) -> dict:
+    return dict(CONFIGS[i])
+
+
+def zipf_sizes(n: int, n_clusters: int, s: float = 1.2) -> np.ndarray:
+    """Cluster sizes proportional to c^-s, largest-remainder rounding, min 1."""
+    w = np.arange(1, n_clusters + 1, dtype=np.float64) ** (-s)
+    raw = n * w / w.sum()
+    base = np.maximum(np.floor(raw).astype(np.int64), 1)
+    short = n - int(base.sum())
+    if short > 0:
+        order = np.argsort(-(raw - np.floor(raw)), kind="stable")
+        base[order[:short]] += 1
+    elif short < 0:
+        order = np.argsort(-base, kind="stable")
+        i = 0
+        while short < 0:
+            j = order[i % n_clusters]
+            if base[j] > 1:
+                base[j] -= 1
+                short += 1
+            i += 1
+    assert int(base.sum()) == n
+    return base
+
+
+def cluster_labels(n: int, n_clusters: int, zipf: bool, seed: int) -> np.ndarray:
+    if zipf:
+        sizes = zipf_sizes(n, n_clusters)
+    else:
+        sizes = np.full(n_clusters, n // n_clusters, dtype=np.int64)
+        sizes[: n - int(sizes.sum())] += 1
+    labels = np.repeat(np.arange(n_clusters, dtype=np.int32), sizes)
+    if zipf:
+        rng = np.random.Generator(np.random.Philox(key=[seed, 0xC1]))
+        labels = labels[rng.permutation(n)]
+    return labels
+
+
+def _gene_params(p: int, n_clusters: int, seed: int):
+    rng = np.random.Generator(np.random.Philox(key=[seed, 0x9E]))
+    B = rng.standard_normal((p, FACTOR_RANK))
+    M = rng.standard_normal((n_clusters, p))
+    g = rng.standard_normal(p) * math.sqrt(0.5)
+    return B, M, g
+
+
+def _block_rows(block: int, n: int, p: int, labels, gene, beta0: float, seed: int):
+    lo = block * ROW_BLOCK
+    hi = min(n, lo + ROW_BLOCK)
+    rng = np.random.Generator(np.random.Philox(key=[seed, 0x5EED0000 + block]))
+    A = rng.standard_normal((hi - lo, FACTOR_RANK))
+    B, M, g = gene
+    log_mu = beta0 + 0.5 * (A @ B.T) / math.sqrt(FACTOR_RANK) + M[labels[lo:hi]] + g[None, :]
+    mu = np.exp(log_mu)
+    # NB(mean mu, dispersion alpha): failures before 1/alpha successes, success prob 1/(1+alpha mu)
+    counts = rng.negative_binomial(1.0 / ALPHA, 1.0 / (1.0 + ALPHA * mu))
+    return np.log1p(counts).astype(np.float32)
+
+
+def _calibrate_beta0(density: float, p: int, n_clusters: int, labels, seed: int) -> float:
+    """beta0 such that the mean probability of a nonzero count equals ``density``."""
+    gene = _gene_params(p, n_clusters, seed)
+    B, M, g = gene
+    rng = np.random.Generator(np.random.Philox(key=[seed, 0xCA1]))
+    m = 1_000_000
+    ii = rng.integers(0, labels.shape[0], m)
+    jj = rng.integers(0, p, m)
+    A = rng.standard_normal((m, FACTOR_RANK))
+    base = 0.5 * np.einsum("mk,mk->m", A, B[jj]) / math.sqrt(FACTOR_RANK) + M[labels[ii], jj] + g[jj]
+
+    def frac(b0):
+        mu = np.exp(b0 + base)
+        return float(np.mean(1.0 - (1.0 + ALPHA * mu) ** (-1.0 / ALPHA)))
+
+    lo, hi = -20.0, 10.0
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        if frac(mid) < density:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def nb_log1p(n: int, p: int, n_clusters: int, zipf: bool, seed: int,
+             beta0: float | None = 0.0, density: float | None = None):
+    """Dense float32 X (n x p) and the cluster labels.  See the module docstring."""
+    labels = cluster_labels(n, n_clusters, zipf, seed)
+    if beta0 is None:
+        beta0 = _calibrate_beta0(density, p, n_clusters, labels, seed)
+    gene = _gene_params(p, n_clusters, seed)
+    X = np.empty((n, p), dtype=np.float32)
+    for b in range((n + ROW_BLOCK - 1) // ROW_BLOCK):
+        lo = b * ROW_BLOCK
+        X[lo:lo + ROW_BLOCK] = _block_rows(b, n, p, labels, gene, beta0, seed)
+    return X, labels, beta0
+
+
+def nb_log1p_rows(rows, n: int, p: int, n_clusters: int, zipf: bool, seed: int, beta0: float):
+    """Regenerate selected rows of ``nb_log1p`` without building the whole matrix."""
+    rows = np.asarray(rows, dtype=np.int64)
+    labels = cluster_labels(n, n_clusters, zipf, seed)
+    gene = _gene_params(p, n_clusters, seed)
+    out = np.empty((rows.shape[0], p), dtype=np.float32)
+    cache = {}
+    for t, i in enumerate(rows):
+        b = int(i) // ROW_BLOCK
+        if b not in cache:
+            cache[b] = _block_rows(b, n, p, labels, gene, beta0, seed)
+        out[t] = cache[b][int(i) - b * ROW_BLOCK]
+    return out
+
+
+def dense_to_csr(X: np.ndarray):
+    """(row_ptr int64, col int32, val float32) of the nonzeros of X, columns ascending."""
+    nz = X != 0
+    row_ptr = np.zeros(X.shape[0] + 1, dtype=np.int64)
+    np.cumsum(nz.sum(axis=1), out=row_ptr[1:])
+    rr, cc = np.nonzero(nz)
+    return row_ptr, cc.astype(np.int32), X[rr, cc].astype(np.float32)
+
+
+def cell_factor_proxy(n: int, r: int, n_clusters: int, seed: int, zipf: bool = True,
+                      noise: float = 1.0) -> np.ndarray:
+    """n x r float32 with orthonormal columns and cell-factor-like rows.
+
+    Columns span [cluster centroids | rank-8 factor | per-cell noise]; rows in
+    one cluster share the centroid part, so near-duplicate cells exist as in
+    clustered single-cell data.
+    """
+    labels = cluster_labels(n, n_clusters, zipf, seed)
+    rng = np.random.Generator(np.random.Philox(key=[seed, 0xFAC7]))
+    n_c = min(n_clusters, max(1, r // 2))
+    n_f = min(FACTOR_RANK, max(0, r - n_c))
+    n_e = r - n_c - n_f
+    parts = []
+    cent = rng.standard_normal((n_clusters, n_c)) * 3.0
+    parts.append(cent[labels])
+    if n_f:
+        parts.append(rng.standard_normal((n, n_f)) * 1.5)
+    if n_e:
+        parts.append(rng.standard_normal((n, n_e)) * noise)
+    Y = np.concatenate(parts, axis=1)
+    Q, R = np.linalg.qr(Y)
+    Q *= np.sign(np.diag(R))[None, :]
+    return np.ascontiguousarray(Q.astype(np.float32))
+
+
+def spectrum_proxy(p: int, n: int, n_spikes: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """Descending spectrum of a p x p Gram of n samples: spikes over an MP bulk."""
+    rng = np.random.Generator(np.random.Philox(key=[seed, 0x5EC7]))
+    q = min(p, n) / max(p, n)
+    lo, hi = (1 - math.sqrt(q)) ** 2, (1 + math.sqrt(q)) ** 2
+    # Marchenko-Pastur quantiles by inverting the CDF on a fine grid
+    x = np.linspace(lo, hi, 200_001)
+    dens = np.sqrt(np.maximum((hi - x) * (x - lo), 0.0)) / (2 * math.pi * q * x)
+    cdf = np.cumsum(dens)
+    cdf /= cdf[-1]
+    m = min(p, n)
+    u = (np.arange(m) + 0.5) / m
+    bulk = np.interp(u, cdf, x) * max(p, n)
+    spikes = hi * max(p, n) * (2.0 + 10.0 * rng.random(n_spikes) ** 2) ** 2
+    e = np.concatenate([spikes, bulk])
+    e = np.sort(e)[::-1][:m] * scale
+    return np.ascontiguousarray(e)
