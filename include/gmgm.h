@@ -1,0 +1,134 @@
+/*
+ * gmgm.h -- C ABI of the MI355X (gfx950) hot path of the multi-axis
+ * Kronecker-sum Gaussian graphical model (arXiv 2407.19892, "Making
+ * Multi-Axis Gaussian Graphical Models Scalable to Millions of Cells").
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller unless marked
+ *     "host".  The library never frees caller memory.  It owns only its
+ *     workspace, held in the context and released by gmgm_destroy.
+ *   - Work is enqueued on the context's HIP stream and the call returns
+ *     without waiting, except where a call is marked "synchronises".
+ *   - No exception crosses the ABI.  Each call returns a gmgm_status; the
+ *     context keeps a message for the last failure (gmgm_last_error).
+ *     Argument and shape checks happen before anything is launched; on such
+ *     an error nothing is enqueued and outputs are untouched.
+ *   - Faults found on the device (non-finite inputs, HIP errors) are reported
+ *     by the next synchronising call (gmgm_sync or a call that synchronises).
+ *   - One context per host thread and stream.  Calls on one context must not
+ *     overlap.
+ */
+#ifndef GMGM_H
+#define GMGM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmgm_ctx* gmgm_ctx_t;
+
+typedef enum {
+  GMGM_OK = 0,
+  GMGM_E_ARG = 1,      /* null pointer, bad enum, out-of-range scalar */
+  GMGM_E_SHAPE = 2,    /* inconsistent sizes */
+  GMGM_E_DOMAIN = 3,   /* non-finite or non-positive input where positive finite is required */
+  GMGM_E_NOCONV = 4,   /* iterative solve hit its iteration limit */
+  GMGM_E_OVERFLOW = 5, /* a fixed-capacity device buffer overflowed */
+  GMGM_E_HIP = 6,      /* HIP runtime or library failure */
+  GMGM_E_NOMEM = 7     /* device allocation failed */
+} gmgm_status;
+
+typedef enum {
+  GMGM_FP32 = 0,      /* FP32 operands, FP32 MFMA (32x32x2) */
+  GMGM_BF16 = 1,      /* BF16 operands, FP32 accumulation (32x32x16) */
+  GMGM_FP8_E4M3 = 2   /* OCP FP8 e4m3 operands with power-of-two row/tile scales,
+                         FP32 accumulation (32x32x64 f8f6f4) */
+} gmgm_prec;
+
+/* Version of this ABI (major * 10000 + minor * 100 + patch). */
+int gmgm_version(void);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL means the legacy default stream).  Synchronises. */
+gmgm_status gmgm_create(gmgm_ctx_t* ctx, int device, void* hip_stream);
+
+/* Release the context and its workspace.  Synchronises.  NULL is ignored. */
+void gmgm_destroy(gmgm_ctx_t ctx);
+
+/* Change the stream later calls enqueue on. */
+gmgm_status gmgm_set_stream(gmgm_ctx_t ctx, void* hip_stream);
+
+/* Message of the last failed call on this context ("" if none).  The string
+ * is owned by the context and valid until the next call on it. */
+const char* gmgm_last_error(gmgm_ctx_t ctx);
+
+/* Wait for all work enqueued by this context and report the first device-side
+ * fault recorded since the previous gmgm_sync (GMGM_E_DOMAIN for non-finite
+ * inputs found by a kernel, GMGM_E_HIP for runtime errors).  Synchronises. */
+gmgm_status gmgm_sync(gmgm_ctx_t ctx);
+
+/* Enable (1) or disable (0) HIP-event timing of each call's dominant kernel
+ * (the MFMA sweep of gmgm_recompose_topk), recorded on the context stream. */
+gmgm_status gmgm_set_timing(gmgm_ctx_t ctx, int enable);
+
+/* Total duration (ms, host) and count (host) of the timed kernels recorded
+ * since the previous query; clears the record.  Synchronises. */
+gmgm_status gmgm_kernel_times(gmgm_ctx_t ctx, double* total_ms, int64_t* count);
+
+/* Counters of one gmgm_recompose_topk call (filled only when requested). */
+typedef struct {
+  int64_t cand_total;       /* candidates (approximate top-C entries) kept by the sweep */
+  int64_t rows_fallback;    /* rows the first sweep could not certify (re-swept in FP32) */
+  int64_t rows_near_tie;    /* certified rows whose k-th and (k+1)-th exact |Psi| differ
+                               by < 1e-6 relative */
+  int64_t rows_exact;       /* rows the FP32 re-sweep could not certify either (exact
+                               FP64 scan of the whole row) */
+  double mfma_flops;        /* MFMA flops executed by the sweeps (padded K) */
+} gmgm_topk_stats;
+
+/*
+ * Fused eigen-recomposition with per-row top-k thresholding into CSR.
+ *
+ * Algorithm 1, final loop ("threshold simultaneously with recomposition"),
+ * with the per-row strongest-edge rule of the experiments: for each row i in
+ * [row_begin, row_end) of Psi = V diag(psi) V^T,
+ *   keep the k columns j != i with the largest |Psi_ij| (ties to smaller j),
+ * without forming Psi.
+ *
+ *   n, r        V is n x r, row-major FP32 (device).  1 <= r <= 128.
+ *   psi         r FP64 eigenvalues (device).
+ *   row_begin, row_end   0 <= row_begin < row_end <= n.
+ *   k           1 <= k <= 24 and k <= n - 1.
+ *   prec        operand precision of the first MFMA sweep (gmgm_prec).  Every
+ *               precision ends the same way: candidates are rescored exactly
+ *               (FP64 from the FP32 V and FP64 psi); rows whose rounding
+ *               margin cannot certify the candidate set are re-swept with FP32
+ *               operands, and rows that still fail are scanned exactly in FP64,
+ *               so the output does not depend on `prec`.
+ *   cand_cap    length of the sweep's per-lane candidate lists (16 or 32;
+ *               0 picks 32 for BF16 / FP8, where a list covers a whole row,
+ *               and 16 for FP32, where a list covers half a row).  Must
+ *               exceed k.
+ *   row_ptr_out (row_end - row_begin + 1) int64: row_ptr[t] = k * t.
+ *   col_out     k * (row_end - row_begin) int32, ascending within a row.
+ *   val_out     k * (row_end - row_begin) FP32: Psi_ij (signed), rounded
+ *               from the FP64 rescoring.
+ *   stats       host pointer or NULL; filled when non-NULL.
+ * The call synchronises once after the first sweep (and once more when rows
+ * need the FP32 re-sweep) to size the re-sweep of uncertified rows.
+ * Non-finite V or psi are reported as GMGM_E_DOMAIN by the next
+ * synchronising call (the outputs are then undefined).
+ */
+gmgm_status gmgm_recompose_topk(gmgm_ctx_t ctx, int64_t n, int64_t r, const float* V,
+                                const double* psi, int64_t row_begin, int64_t row_end,
+                                int32_t k, gmgm_prec prec, int32_t cand_cap,
+                                int64_t* row_ptr_out, int32_t* col_out, float* val_out,
+                                gmgm_topk_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMGM_H */

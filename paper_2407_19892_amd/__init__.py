@@ -1,0 +1,166 @@
+"""Python binding of libgmgm, the gfx950 HIP hot path of the multi-axis
+Kronecker-sum Gaussian graphical model (arXiv 2407.19892).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Torch provides device memory (output tensors) and the current HIP stream.
+Loading fails loudly when the library has not been built; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmgm.so")
+
+PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_SHAPE", 3: "E_DOMAIN", 4: "E_NOCONV", 5: "E_OVERFLOW",
+          6: "E_HIP", 7: "E_NOMEM"}
+
+_lib = None
+_ctx = {}
+
+
+class GmgmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gmgm {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class TopkStats(ctypes.Structure):
+    _fields_ = [("cand_total", ctypes.c_int64), ("rows_fallback", ctypes.c_int64),
+                ("rows_near_tie", ctypes.c_int64), ("rows_exact", ctypes.c_int64),
+                ("mfma_flops", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "gmgm_version": (ctypes.c_int, []),
+    "gmgm_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
+    "gmgm_destroy": (None, [_P]),
+    "gmgm_set_stream": (ctypes.c_int, [_P, _P]),
+    "gmgm_last_error": (ctypes.c_char_p, [_P]),
+    "gmgm_sync": (ctypes.c_int, [_P]),
+    "gmgm_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gmgm_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "gmgm_recompose_topk": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, _I64, _I32, ctypes.c_int,
+                                           _I32, _P, _P, _P, ctypes.POINTER(TopkStats)]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libgmgm.so (raises if it is missing: build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _stream_handle(device):
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def context(device=None):
+    """The library context of `device`, re-pointed at torch's current stream."""
+    import torch
+    lib = load()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    st = _stream_handle(dev)
+    c = _ctx.get(dev)
+    if c is None:
+        h = _P()
+        s = lib.gmgm_create(ctypes.byref(h), dev, _P(st))
+        if s != 0:
+            raise GmgmError(s, f"gmgm_create(device={dev}) failed")
+        c = h
+        _ctx[dev] = c
+    else:
+        _check(c, lib.gmgm_set_stream(c, _P(st)))
+    return c
+
+
+def _check(c, status):
+    if status != 0:
+        raise GmgmError(status, load().gmgm_last_error(c).decode())
+
+
+def _ptr(t):
+    return _P(t.data_ptr())
+
+
+def sync(device=None):
+    c = context(device)
+    _check(c, load().gmgm_sync(c))
+
+
+def set_timing(enable: bool, device=None):
+    c = context(device)
+    _check(c, load().gmgm_set_timing(c, 1 if enable else 0))
+
+
+def kernel_times(device=None):
+    """(total ms, count) of the timed dominant-kernel launches since the last query."""
+    c = context(device)
+    tot = ctypes.c_double()
+    cnt = _I64()
+    _check(c, load().gmgm_kernel_times(c, ctypes.byref(tot), ctypes.byref(cnt)))
+    return tot.value, cnt.value
+
+
+@dataclass
+class TopkResult:
+    row_ptr: "object"
+    col: "object"
+    val: "object"
+    stats: dict | None = None
+
+
+def recompose_topk(V, psi, k: int, prec: str = "bf16", row_begin: int = 0, row_end: int | None = None,
+                   cand_cap: int = 0, stats: bool = False, check: bool = True, out=None) -> TopkResult:
+    """CSR of the per-row top-k of Psi = V diag(psi) V^T (see gmgm_recompose_topk)."""
+    import torch
+    if not (V.is_cuda and psi.is_cuda):
+        raise ValueError("V and psi must be device tensors")
+    if V.dtype != torch.float32 or psi.dtype != torch.float64:
+        raise TypeError("V must be float32 and psi float64")
+    if not V.is_contiguous() or not psi.is_contiguous() or V.dim() != 2:
+        raise ValueError("V must be a contiguous 2-D tensor and psi contiguous")
+    n, r = V.shape
+    if psi.numel() != r:
+        raise ValueError("psi must have r entries")
+    row_end = n if row_end is None else row_end
+    rows = max(0, row_end - row_begin)
+    if out is None:
+        rp = torch.empty(rows + 1, dtype=torch.int64, device=V.device)
+        col = torch.empty(rows * k, dtype=torch.int32, device=V.device)
+        val = torch.empty(rows * k, dtype=torch.float32, device=V.device)
+    else:
+        rp, col, val = out
+    c = context(V.device.index)
+    st = TopkStats() if stats else None
+    _check(c, load().gmgm_recompose_topk(c, n, r, _ptr(V), _ptr(psi), row_begin, row_end, k, PREC[prec],
+                                          cand_cap, _ptr(rp), _ptr(col), _ptr(val),
+                                          ctypes.byref(st) if st is not None else None))
+    if check:
+        _check(c, load().gmgm_sync(c))
+    sd = None
+    if st is not None:
+        sd = {"cand_total": st.cand_total, "rows_fallback": st.rows_fallback,
+              "rows_near_tie": st.rows_near_tie, "rows_exact": st.rows_exact,
+              "mfma_flops": st.mfma_flops}
+    return TopkResult(rp, col, val, sd)

@@ -1,0 +1,163 @@
+// Context, errors, workspace and synchronisation of the C ABI.
+#include "gmgm_internal.h"
+
+gmgm_status set_err(gmgm_ctx* c, gmgm_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+gmgm_status hip_err(gmgm_ctx* c, hipError_t e, const char* what) {
+  return set_err(c, e == hipErrorOutOfMemory ? GMGM_E_NOMEM : GMGM_E_HIP, "%s: %s", what,
+                 hipGetErrorString(e));
+}
+
+gmgm_status ws_get(gmgm_ctx* c, int slot, size_t bytes, void** out) {
+  if (slot < 0 || slot >= WS_COUNT) return set_err(c, GMGM_E_ARG, "bad workspace slot");
+  if (c->bufs.size() < WS_COUNT) c->bufs.resize(WS_COUNT);
+  DevBuf& b = c->bufs[slot];
+  if (bytes == 0) bytes = 256;
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      // the old buffer may still be read by queued kernels
+      GMGM_HIP(c, hipStreamSynchronize(c->stream));
+      GMGM_HIP(c, hipFree(b.ptr));
+      b.ptr = nullptr;
+      b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    hipError_t e = hipMalloc(&b.ptr, want);
+    if (e != hipSuccess) {
+      b.ptr = nullptr;
+      return set_err(c, GMGM_E_NOMEM, "workspace allocation of %zu bytes failed: %s", want,
+                     hipGetErrorString(e));
+    }
+    b.bytes = want;
+  }
+  *out = b.ptr;
+  return GMGM_OK;
+}
+
+extern "C" int gmgm_version(void) { return 100; }
+
+extern "C" gmgm_status gmgm_create(gmgm_ctx_t* out, int device, void* stream) {
+  if (!out) return GMGM_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GMGM_E_ARG;
+  gmgm_ctx* c = new gmgm_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipMalloc(&c->dev_status, sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&c->host_status, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipMemset(c->dev_status, 0, sizeof(int)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    if (c->dev_status) (void)hipFree(c->dev_status);
+    if (c->host_status) (void)hipHostFree(c->host_status);
+    delete c;
+    return GMGM_E_HIP;
+  }
+  c->bufs.resize(WS_COUNT);
+  *out = c;
+  return GMGM_OK;
+}
+
+
+static hipEvent_t pool_event(gmgm_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+hipEvent_t timing_start(gmgm_ctx* c) {
+  if (!c->timing) return nullptr;
+  hipEvent_t e = pool_event(c);
+  if (e && hipEventRecord(e, c->stream) != hipSuccess) return nullptr;
+  return e;
+}
+
+void timing_stop(gmgm_ctx* c, hipEvent_t start) {
+  if (!start) return;
+  hipEvent_t e = pool_event(c);
+  if (!e || hipEventRecord(e, c->stream) != hipSuccess) return;
+  c->timed.emplace_back(start, e);
+}
+
+extern "C" gmgm_status gmgm_set_timing(gmgm_ctx_t c, int enable) {
+  GMGM_CHECK_CTX(c);
+  c->timing = enable != 0;
+  return GMGM_OK;
+}
+
+extern "C" gmgm_status gmgm_kernel_times(gmgm_ctx_t c, double* total_ms, int64_t* count) {
+  GMGM_CHECK_CTX(c);
+  if (!total_ms || !count) return set_err(c, GMGM_E_ARG, "null output pointer");
+  GMGM_HIP(c, hipSetDevice(c->device));
+  GMGM_HIP(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (auto& p : c->timed) {
+    float ms = 0.0f;
+    GMGM_HIP(c, hipEventElapsedTime(&ms, p.first, p.second));
+    tot += ms;
+    c->ev_pool.push_back(p.first);
+    c->ev_pool.push_back(p.second);
+  }
+  *total_ms = tot;
+  *count = (int64_t)c->timed.size();
+  c->timed.clear();
+  return GMGM_OK;
+}
+
+extern "C" void gmgm_destroy(gmgm_ctx_t c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& p : c->timed) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto& b : c->bufs)
+    if (b.ptr) (void)hipFree(b.ptr);
+  (void)hipFree(c->dev_status);
+  (void)hipHostFree(c->host_status);
+  delete c;
+}
+
+extern "C" gmgm_status gmgm_set_stream(gmgm_ctx_t c, void* stream) {
+  GMGM_CHECK_CTX(c);
+  c->stream = (hipStream_t)stream;
+  return GMGM_OK;
+}
+
+extern "C" const char* gmgm_last_error(gmgm_ctx_t c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" gmgm_status gmgm_sync(gmgm_ctx_t c) {
+  GMGM_CHECK_CTX(c);
+  GMGM_HIP(c, hipSetDevice(c->device));
+  GMGM_HIP(c, hipMemcpyAsync(c->host_status, c->dev_status, sizeof(int), hipMemcpyDeviceToHost,
+                             c->stream));
+  GMGM_HIP(c, hipStreamSynchronize(c->stream));
+  GMGM_HIP(c, hipGetLastError());
+  int s = *c->host_status;
+  if (s != DEV_OK) {
+    GMGM_HIP(c, hipMemsetAsync(c->dev_status, 0, sizeof(int), c->stream));
+    GMGM_HIP(c, hipStreamSynchronize(c->stream));
+    if (s == DEV_NONFINITE) return set_err(c, GMGM_E_DOMAIN, "a kernel found a non-finite input");
+    if (s == DEV_OVERFLOW) return set_err(c, GMGM_E_OVERFLOW, "a device buffer overflowed");
+    return set_err(c, GMGM_E_HIP, "device fault code %d", s);
+  }
+  return GMGM_OK;
+}

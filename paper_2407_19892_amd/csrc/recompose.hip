@@ -1,0 +1,776 @@
+// Fused eigen-recomposition Psi = V diag(psi) V^T with per-row top-k into CSR
+// (Algorithm 1, final loop: threshold while recomposing; per-row strongest
+// edges as in the experiments).  Psi is never materialised.
+//
+// Pipeline of one call (all on the context stream):
+//   prep      row norms, row maxima, non-finite check           (HBM, reads V once)
+//   repack    W = V diag(psi) and V into MFMA operand tiles      (HBM)
+//   sweep     each wave keeps W for 32*TI rows in registers and streams all
+//             32-row tiles of V through MFMA; every lane keeps a sorted top-C
+//             list (approximate |Psi|) per row it holds      (MFMA-bound)
+//   finalize  one wave per row: rescore the candidates exactly (FP64), take
+//             the top k, certify that no column outside the candidates can
+//             beat the k-th with the precision's rounding bound, emit CSR
+//   fallback  rows that fail the certificate: exact FP64 scan of the whole row
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "recompose_sweep.h"
+
+namespace gmgm_rc {
+
+// ------------------------------------------------------------------ prep
+// One wave per row (grid-stride): ||V_j|| max-reduced into vmax_bits (one
+// atomic per workgroup), max|V_j|, and for rows in [w_lo, w_hi) the norm and
+// max of W_i = V_i * psi.  Flags non-finite inputs.
+__global__ void __launch_bounds__(256) prep_kernel(const float* __restrict__ V,
+                                                   const double* __restrict__ psi, int64_t n,
+                                                   int r, int64_t w_lo, int64_t w_hi,
+                                                   float* __restrict__ vrowmax,
+                                                   double* __restrict__ wnorm,
+                                                   float* __restrict__ wrowmax,
+                                                   unsigned* __restrict__ vmax_bits,
+                                                   int* __restrict__ status) {
+  __shared__ float bmax[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  float nmax = 0.0f;
+  bool bad = false;
+  for (int64_t j = (int64_t)blockIdx.x * 4 + wave; j < n; j += (int64_t)gridDim.x * 4) {
+    double s = 0.0, sw = 0.0;
+    float mx = 0.0f, mw = 0.0f;
+    const bool inw = j >= w_lo && j < w_hi;
+    for (int k = lane; k < r; k += 64) {
+      const float x = V[j * r + k];
+      bad |= !isfinite(x);
+      s += (double)x * (double)x;
+      mx = fmaxf(mx, fabsf(x));
+      if (inw) {
+        const double pk = psi[k];
+        bad |= !isfinite(pk);
+        const double w = (double)x * pk;
+        sw += w * w;
+        mw = fmaxf(mw, fabsf((float)w));
+      }
+    }
+    s = wave_sum_f64(s);
+    mx = wave_max_f32(mx);
+    nmax = fmaxf(nmax, (float)sqrt(s));
+    if (!(s == s)) nmax = __builtin_nanf("");
+    if (lane == 0) vrowmax[j] = mx;
+    if (inw) {
+      sw = wave_sum_f64(sw);
+      mw = wave_max_f32(mw);
+      if (lane == 0) {
+        wnorm[j - w_lo] = sqrt(sw);
+        wrowmax[j - w_lo] = mw;
+      }
+    }
+  }
+  if (__ballot(bad) && lane == 0) atomicCAS(status, 0, DEV_NONFINITE);
+  if (lane == 0) bmax[wave] = nmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = fmaxf(fmaxf(bmax[0], bmax[1]), fmaxf(bmax[2], bmax[3]));
+    // non-negative floats order like their bit patterns; NaN (0x7fc...) wins
+    atomicMax(vmax_bits, __float_as_uint(m));
+  }
+}
+
+// Smallest e with maxabs <= 448 * 2^e (power-of-two scale of an FP8 e4m3 row / tile).
+__device__ inline int fp8_exp(float maxabs) {
+  if (!(maxabs > 0.0f) || !isfinite(maxabs)) return 0;
+  int e;
+  frexpf(maxabs / 448.0f, &e);
+  if (__builtin_ldexpf(maxabs, -(e - 1)) <= 448.0f) e -= 1;
+  while (__builtin_ldexpf(maxabs, -e) > 448.0f) e += 1;
+  return e;
+}
+
+__global__ void fp8_exps_kernel(const float* __restrict__ vrowmax, int64_t n, int n_vtiles,
+                                const float* __restrict__ wrowmax, int64_t n_wrows,
+                                int* __restrict__ ev, int* __restrict__ ew) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_vtiles) {
+    float m = 0.0f;
+    for (int q = 0; q < 32; ++q) {
+      int64_t j = t * 32 + q;
+      if (j < n) m = fmaxf(m, vrowmax[j]);
+    }
+    ev[t] = fp8_exp(m);
+  }
+  if (t < n_wrows) ew[t] = fp8_exp(wrowmax[t]);
+}
+
+// ------------------------------------------------------------------ repack
+// One thread per (local row, 16-byte chunk) of `rows` local rows.  Local row w
+// is global row row0 + w, or row_list[w] (w < *row_count) in list mode; rows
+// outside [0, n) and k >= r are zero.
+template <int PREC>
+__global__ void repack_kernel(const float* __restrict__ V, const double* __restrict__ psi,
+                              int64_t row0, int64_t n, int64_t rows, int r, int kpad,
+                              bool fold_psi, const int* __restrict__ exps, bool exp_per_tile,
+                              const int* __restrict__ row_list, const int* __restrict__ row_count,
+                              u32x4* __restrict__ out) {
+  constexpr int ECH = chunk_elems(PREC);
+  const int nch = kpad / ECH;
+  const int units = nch / 2;     // chunks per lane per tile
+  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= rows * nch) return;
+  const int64_t w = gid / nch;
+  int64_t row;
+  if (row_list) {
+    const int cnt = *row_count;
+    if (w >= ((int64_t)cnt + 31) / 32 * 32) return;   // beyond the listed tiles
+    row = w < cnt ? row_list[w] : -1;
+  } else {
+    row = row0 + w;
+  }
+  const int ch = (int)(gid % nch);
+  const int k0 = ch * ECH;
+  int u, h;
+  if (PREC == P_F32) { u = k0 / 8; h = (k0 / 4) & 1; }
+  else if (PREC == P_BF16) { u = k0 / 16; h = (k0 / 8) & 1; }
+  else { u = 2 * (k0 / 64) + ((k0 / 16) & 1); h = (k0 / 32) & 1; }
+  float x[ECH];
+#pragma unroll
+  for (int e = 0; e < ECH; ++e) {
+    const int k = k0 + e;
+    float v = 0.0f;
+    if (row >= 0 && row < n && k < r) {
+      const float vv = V[row * r + k];
+      v = fold_psi ? (float)((double)vv * psi[k]) : vv;
+    }
+    x[e] = v;
+  }
+  u32x4 o;
+  if (PREC == P_F32) {
+    o = u32x4{__float_as_uint(x[0]), __float_as_uint(x[1]), __float_as_uint(x[2]),
+              __float_as_uint(x[3])};
+  } else if (PREC == P_BF16) {
+    unsigned q[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      q[e] = (unsigned)f32_to_bf16_bits(x[2 * e]) | ((unsigned)f32_to_bf16_bits(x[2 * e + 1]) << 16);
+    o = u32x4{q[0], q[1], q[2], q[3]};
+  } else {
+    const int sc = exp_per_tile ? exps[w / 32] : exps[w];
+    unsigned q[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      unsigned b = 0;
+#pragma unroll
+      for (int z = 0; z < 4; ++z) {
+        float y = __builtin_ldexpf(x[4 * e + z], -sc);
+        y = isfinite(y) ? y : 0.0f;          // non-finite inputs are already flagged
+        b |= (unsigned)f32_to_e4m3_bits(fminf(fmaxf(y, -448.0f), 448.0f)) << (8 * z);
+      }
+      q[e] = b;
+    }
+    o = u32x4{q[0], q[1], q[2], q[3]};
+  }
+  const int64_t tile = w / 32;
+  out[(tile * units + u) * 64 + (w % 32) + 32 * h] = o;
+}
+
+// ------------------------------------------------------------------ finalize
+// One wave per row.  The row's candidates are S*nsub sublists of C entries
+// (descending approximate |Psi|, INVALID_J padded), one per column split and,
+// when the sweep kept half rows, lane half.  With beta = cprec ||W_i|| max_j ||V_j|| bounding |approx - exact|:
+//   A_k   = k-th largest approximate value among the candidates;
+//   R     = candidates with approx >= A_k - 2 beta, rescored exactly (FP64);
+//   T     = k-th largest exact |Psi| in R (ties to smaller j);
+//   m_out = largest approximate value any non-candidate can have (the last
+//           entry of every full sublist).
+// Certified when m_out + beta < T: every column outside R has exact < T.
+// Uncertified rows are appended (as global rows) to fail_list.
+struct FinalArgs {
+  const float* cval;
+  const int* cidx;
+  const float* V;
+  const double* psi;
+  const double* wnorm;       // per W row, indexed by global row - w_lo
+  const unsigned* vmax_bits;
+  int64_t n;
+  int r, k, C, S, nsub;
+  int64_t row_begin, rows;   // contiguous mode: slot s is row row_begin + s
+  int64_t w_lo;
+  const int* row_list;       // list mode: slot s is row row_list[s], s < *row_count
+  const int* row_count;
+  double cprec;
+  int32_t* col_out;
+  float* val_out;
+  int* fail_list;
+  int* fail_count;
+  unsigned long long* counters;   // [0] candidates, [1] near ties (certified rows)
+};
+
+constexpr int MAXK = 32;
+constexpr int RCAP = 256;   // exact rescoring capacity per row
+
+__device__ inline bool key_greater(double av, int aj, double bv, int bj) {
+  return av > bv || (av == bv && aj < bj);
+}
+
+__device__ inline unsigned long long approx_key(float v, int j) {
+  return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned)(0x7fffffff - j);
+}
+
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
+  __shared__ double wrow[4][128];
+  __shared__ double rv[4][RCAP];
+  __shared__ int rj[4][RCAP];
+  __shared__ double sel_v[4][MAXK + 1];
+  __shared__ int sel_j[4][MAXK + 1];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
+  int64_t i;
+  if (a.row_list) {
+    if (slot >= *a.row_count) return;
+    i = a.row_list[slot];
+  } else {
+    if (slot >= a.rows) return;
+    i = a.row_begin + slot;
+  }
+  const int64_t loc = i - a.row_begin;
+  const int M = a.S * a.nsub * a.C;
+  const int64_t cbase = slot * M;
+
+  for (int q = lane; q < a.r; q += 64) wrow[wave][q] = (double)a.V[i * a.r + q] * a.psi[q];
+
+  float mout = -1.0f;
+  for (int q = lane; q < a.S * a.nsub; q += 64) {
+    const int64_t e = cbase + (int64_t)q * a.C + a.C - 1;
+    if (a.cidx[e] != INVALID_J) mout = fmaxf(mout, a.cval[e]);
+  }
+  mout = wave_max_f32(mout);
+
+  // k-th largest approximate key among the candidates
+  int nvalid = 0;
+  for (int q = lane; q < M; q += 64) nvalid += a.cidx[cbase + q] != INVALID_J;
+  nvalid = wave_sum_i32(nvalid);
+  unsigned long long prev = ~0ull;
+  int found = 0;
+  for (int t = 0; t < a.k; ++t) {
+    unsigned long long best = 0;
+    for (int q = lane; q < M; q += 64) {
+      const int j = a.cidx[cbase + q];
+      if (j == INVALID_J) continue;
+      const unsigned long long key = approx_key(a.cval[cbase + q], j);
+      if (key < prev && key > best) best = key;
+    }
+    best = wave_max_u64(best);
+    if (best == 0) break;
+    prev = best;
+    found++;
+  }
+  const float ak = found == a.k ? __uint_as_float((unsigned)(prev >> 32)) : -1.0f;
+  const double vmax = (double)__uint_as_float(*a.vmax_bits);
+  const double beta = a.cprec * a.wnorm[i - a.w_lo] * vmax;
+  const double thr = (double)ak - 2.0 * beta;
+
+  // rescoring set R, compacted into LDS
+  int rc = 0;
+  __builtin_amdgcn_wave_barrier();
+  for (int base = 0; base < M; base += 64) {
+    const int q = base + lane;
+    bool take = false;
+    int j = INVALID_J;
+    if (q < M) {
+      j = a.cidx[cbase + q];
+      take = j != INVALID_J && (double)a.cval[cbase + q] >= thr;
+    }
+    const unsigned long long mask = __ballot(take);
+    const int pos = rc + __popcll(mask & ((1ull << lane) - 1ull));
+    if (take && pos < RCAP) {
+      const float* vj = a.V + (int64_t)j * a.r;
+      double s = 0.0;
+      for (int kk = 0; kk < a.r; ++kk) s = fma(wrow[wave][kk], (double)vj[kk], s);
+      rv[wave][pos] = s;
+      rj[wave][pos] = j;
+    }
+    rc += __popcll(mask);
+  }
+  __builtin_amdgcn_wave_barrier();
+  const bool overflow = rc > RCAP;
+  const int nr = rc < RCAP ? rc : RCAP;
+
+  // exact top-(k + 1) of R by (|value| desc, j asc)
+  double pv = __builtin_inf();
+  int pj = -1;
+  int nsel = 0;
+  for (int t = 0; t <= a.k; ++t) {
+    double bv = -1.0, bs = 0.0;
+    int bj = INVALID_J;
+    for (int q = lane; q < nr; q += 64) {
+      const double av = fabs(rv[wave][q]);
+      const int j = rj[wave][q];
+      if (key_greater(pv, pj, av, j) && key_greater(av, j, bv, bj)) {
+        bv = av;
+        bj = j;
+        bs = rv[wave][q];
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oj = __shfl_xor(bj, o, 64);
+      const double os = __shfl_xor(bs, o, 64);
+      if (key_greater(ov, oj, bv, bj)) {
+        bv = ov;
+        bj = oj;
+        bs = os;
+      }
+    }
+    if (bj == INVALID_J) break;
+    if (lane == 0) {
+      sel_v[wave][t] = bs;
+      sel_j[wave][t] = bj;
+    }
+    pv = bv;
+    pj = bj;
+    nsel++;
+  }
+  __builtin_amdgcn_wave_barrier();
+  bool ok = !overflow && nsel >= a.k;
+  double tk = 0.0;
+  if (ok) {
+    tk = fabs(sel_v[wave][a.k - 1]);
+    if (mout >= 0.0f) ok = (double)mout + beta < tk;
+  }
+  if (lane == 0) {
+    atomicAdd(&a.counters[0], (unsigned long long)nvalid);
+    if (ok && nsel > a.k && tk - fabs(sel_v[wave][a.k]) <= 1e-6 * tk) atomicAdd(&a.counters[1], 1ull);
+    if (!ok) {
+      const int pos = atomicAdd(a.fail_count, 1);
+      a.fail_list[pos] = (int)i;
+    }
+  }
+  if (!ok) return;
+  if (lane < a.k) {
+    const int jt = sel_j[wave][lane];
+    int rank = 0;
+    for (int u = 0; u < a.k; ++u) rank += sel_j[wave][u] < jt;
+    a.col_out[loc * a.k + rank] = jt;
+    a.val_out[loc * a.k + rank] = (float)sel_v[wave][lane];
+  }
+}
+
+// ------------------------------------------------------------------ exact scan
+// Exact FP64 top-k of whole rows (global rows in `list`); one workgroup per row.
+__global__ void __launch_bounds__(256) exact_scan_kernel(const float* __restrict__ V,
+                                                         const double* __restrict__ psi, int64_t n,
+                                                         int r, int k, int64_t row_begin,
+                                                         const int* __restrict__ list,
+                                                         const int* __restrict__ count,
+                                                         int32_t* __restrict__ col_out,
+                                                         float* __restrict__ val_out) {
+  __shared__ double wrow[128];
+  __shared__ double red_v[256];
+  __shared__ int red_j[256];
+  __shared__ int red_t[256];
+  __shared__ double sel_v[MAXK];
+  __shared__ int sel_j[MAXK];
+  const int tid = threadIdx.x;
+  const int cnt = *count;
+  for (int f = blockIdx.x; f < cnt; f += gridDim.x) {
+    const int64_t i = list[f];
+    const int64_t loc = i - row_begin;
+    __syncthreads();
+    for (int q = tid; q < r; q += 256) wrow[q] = (double)V[i * r + q] * psi[q];
+    __syncthreads();
+    double lv[MAXK];
+    int li[MAXK];
+#pragma unroll
+    for (int s = 0; s < MAXK; ++s) {
+      lv[s] = -1.0;
+      li[s] = INVALID_J;
+    }
+    for (int64_t j = tid; j < n; j += 256) {
+      if (j == i) continue;
+      const float* vj = V + j * r;
+      double s = 0.0;
+      for (int kk = 0; kk < r; ++kk) s = fma(wrow[kk], (double)vj[kk], s);
+      const double x = fabs(s);
+      if (x > lv[MAXK - 1]) {
+        bool gt[MAXK];
+#pragma unroll
+        for (int q = 0; q < MAXK; ++q) gt[q] = x > lv[q];
+#pragma unroll
+        for (int q = MAXK - 1; q > 0; --q) {
+          const double nv = gt[q - 1] ? lv[q - 1] : (gt[q] ? x : lv[q]);
+          const int nj = gt[q - 1] ? li[q - 1] : (gt[q] ? (int)j : li[q]);
+          lv[q] = nv;
+          li[q] = nj;
+        }
+        lv[0] = gt[0] ? x : lv[0];
+        li[0] = gt[0] ? (int)j : li[0];
+      }
+    }
+    // k rounds of block argmax over the heads of the per-thread lists
+    int head = 0;
+    for (int t = 0; t < k; ++t) {
+      double hv = -1.0;
+      int hj = INVALID_J;
+#pragma unroll
+      for (int q = 0; q < MAXK; ++q)
+        if (q == head) {
+          hv = lv[q];
+          hj = li[q];
+        }
+      red_v[tid] = hv;
+      red_j[tid] = hj;
+      red_t[tid] = tid;
+      __syncthreads();
+      for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o && key_greater(red_v[tid + o], red_j[tid + o], red_v[tid], red_j[tid])) {
+          red_v[tid] = red_v[tid + o];
+          red_j[tid] = red_j[tid + o];
+          red_t[tid] = red_t[tid + o];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) sel_j[t] = red_j[0];
+      if (tid == red_t[0]) head++;
+      __syncthreads();
+    }
+    // Signed values and CSR order.  A selection is INVALID_J only when the row
+    // has fewer than k comparable (non-NaN) values, i.e. with non-finite inputs,
+    // which prep has flagged; such slots are never dereferenced.
+    if (tid < k) {
+      const int jt = sel_j[tid];
+      double s = __builtin_nan("");
+      if (jt != INVALID_J) {
+        const float* vj = V + (int64_t)jt * r;
+        s = 0.0;
+        for (int kk = 0; kk < r; ++kk) s = fma(wrow[kk], (double)vj[kk], s);
+      }
+      sel_v[tid] = s;
+    }
+    __syncthreads();
+    if (tid < k) {
+      const int jt = sel_j[tid];
+      if (jt == INVALID_J) {            // invalid selections come last: slot tid is free
+        col_out[loc * k + tid] = -1;
+        val_out[loc * k + tid] = __builtin_nanf("");
+      } else {
+        int rank = 0;
+        for (int u = 0; u < k; ++u) rank += sel_j[u] < jt;
+        col_out[loc * k + rank] = jt;
+        val_out[loc * k + rank] = (float)sel_v[tid];
+      }
+    }
+  }
+}
+
+__global__ void row_ptr_kernel(int64_t* __restrict__ rp, int64_t rows, int k) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t <= rows) rp[t] = t * k;
+}
+
+// ------------------------------------------------------------------ dispatch
+int kpad_for(int prec, int r) {
+  static const int f32[] = {32, 64, 104, 128};
+  static const int bf16[] = {32, 64, 112, 128};
+  static const int fp8[] = {64, 128};
+  const int* t = prec == P_F32 ? f32 : prec == P_BF16 ? bf16 : fp8;
+  int cnt = prec == P_FP8 ? 2 : 4;
+  for (int q = 0; q < cnt; ++q)
+    if (t[q] >= r) return t[q];
+  return -1;
+}
+
+SweepFn pick_sweep(int prec, int kpad, int C) {
+  if (prec == P_F32) return C == 16 ? pick_sweep_f32_c16(kpad) : pick_sweep_f32_c32(kpad);
+  if (prec == P_BF16) return C == 16 ? pick_sweep_bf16_c16(kpad) : pick_sweep_bf16_c32(kpad);
+  return C == 16 ? pick_sweep_fp8_c16(kpad) : pick_sweep_fp8_c32(kpad);
+}
+
+
+// Rounding bound c with |Psi~_ij - Psi_ij| <= c ||W_i||_2 max_j ||V_j||_2 (see header).
+double cprec_for(int prec, int kpad) {
+  const double u32 = std::ldexp(1.0, -24);
+  const double K = kpad + 1;
+  const double gam = K * u32 / (1.0 - K * u32);
+  double c;
+  if (prec == P_F32) {
+    c = (1 + u32) * (1 + gam) - 1 + gam;          // W rounding; products and sums rounded
+  } else if (prec == P_BF16) {
+    const double d = std::ldexp(1.0, -9);
+    const double dw = (1 + u32) * (1 + d) - 1;
+    c = (1 + dw) * (1 + d) * (1 + gam) - 1;        // bf16 products are exact in FP32
+  } else {
+    const double d = std::ldexp(1.0, -4);
+    const double dw = (1 + u32) * (1 + d) - 1;
+    const double fl = std::ldexp(1.0, -10) / 224.0; // subnormal floor per unit of row/tile max
+    c = (1 + dw) * (1 + d) * (1 + gam) - 1 + 2 * (1 + d) * std::sqrt((double)kpad) * fl * (1 + gam) +
+        kpad * fl * fl;
+  }
+  return c * (1 + 1e-6) + 1e-12;
+}
+
+// Split the columns so that the grid has about `target` workgroups, keeping
+// at least two LDS stages per split.
+static int pick_splits(int64_t gx, int n_vtiles, int smax, int64_t target) {
+  int S = 1;
+  while (S < smax && gx * S < target && (int64_t)n_vtiles >= (int64_t)(2 * S) * 8) S *= 2;
+  return S;
+}
+
+struct StageBufs {
+  const u32x4* vp;
+  const u32x4* wp;
+  float* cval;
+  int* cidx;
+};
+
+static gmgm_status stage_buffers(gmgm_ctx* c, int slot_wp, int slot_cand, int64_t wtiles, int units,
+                                 int64_t slots, int S, int nsub, int C, StageBufs* b) {
+  void *wp, *cand;
+  const size_t ncand = (size_t)slots * S * nsub * C;
+  GMGM_TRY(ws_get(c, slot_wp, (size_t)wtiles * units * 64 * 16, &wp));
+  GMGM_TRY(ws_get(c, slot_cand, ncand * 8, &cand));
+  b->wp = (const u32x4*)wp;
+  b->cval = (float*)cand;
+  b->cidx = (int*)((char*)cand + ncand * 4);
+  return GMGM_OK;
+}
+
+template <class F>
+static void launch_repack(int prec, F&& f) {
+  if (prec == P_F32) f(repack_kernel<P_F32>);
+  else if (prec == P_BF16) f(repack_kernel<P_BF16>);
+  else f(repack_kernel<P_FP8>);
+}
+
+}  // namespace gmgm_rc
+
+using namespace gmgm_rc;
+
+extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, const float* V,
+                                           const double* psi, int64_t row_begin, int64_t row_end,
+                                           int32_t k, gmgm_prec prec_e, int32_t cand_cap,
+                                           int64_t* row_ptr_out, int32_t* col_out, float* val_out,
+                                           gmgm_topk_stats* stats) {
+  GMGM_CHECK_CTX(c);
+  const int prec = (int)prec_e;
+  if (prec < 0 || prec > 2) return set_err(c, GMGM_E_ARG, "unknown precision %d", prec);
+  if (n < 2 || n > 0x7ffffff0LL) return set_err(c, GMGM_E_SHAPE, "n = %lld out of range", (long long)n);
+  if (r < 1 || r > 128) return set_err(c, GMGM_E_SHAPE, "r = %lld must be in [1, 128]", (long long)r);
+  if (row_begin < 0 || row_end > n || row_begin >= row_end)
+    return set_err(c, GMGM_E_SHAPE, "row range [%lld, %lld) invalid for n = %lld",
+                   (long long)row_begin, (long long)row_end, (long long)n);
+  if (!V || !psi || !row_ptr_out || !col_out || !val_out)
+    return set_err(c, GMGM_E_ARG, "null pointer argument");
+  if (k < 1 || k > 24 || k > n - 1)
+    return set_err(c, GMGM_E_ARG, "k = %d must be in [1, min(24, n-1)]", k);
+  // Default list length: 32 per full row (BF16 / FP8 sweeps) or 16 per half row
+  // (FP32 sweep): both leave 32 candidates per row.
+  const int C = cand_cap != 0 ? cand_cap : (prec != P_F32 || k > 12) ? 32 : 16;
+  if (C != 16 && C != 32) return set_err(c, GMGM_E_ARG, "cand_cap must be 0, 16 or 32");
+  if (C <= k) return set_err(c, GMGM_E_ARG, "cand_cap %d must exceed k = %d", C, k);
+  GMGM_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+
+  const int kpad = kpad_for(prec, (int)r);
+  SweepFn sweep = pick_sweep(prec, kpad, C);
+  if (!sweep) return set_err(c, GMGM_E_SHAPE, "no sweep variant for r = %lld", (long long)r);
+  const int TI = ti_for(prec, C);
+  const int units = kpad / chunk_elems(prec) / 2;
+  const int64_t rows = row_end - row_begin;
+  const int n_vtiles = (int)ceil_div(n, 32);
+  const int rt_begin = (int)(row_begin / 32);
+  const int rt_end = (int)ceil_div(row_end, 32);
+  const int n_wtiles = rt_end - rt_begin;
+  const int64_t w_lo = (int64_t)rt_begin * 32;
+  const int64_t w_rows = (int64_t)n_wtiles * 32;
+  const int64_t gx = ceil_div(n_wtiles, (int64_t)SW_WAVES * TI);
+  const int S = pick_splits(gx, n_vtiles, 16, 1024);
+  const int tps = (int)ceil_div(n_vtiles, S);
+
+  // ---- workspace
+  void *vp, *norms, *misc, *lists, *scl;
+  GMGM_TRY(ws_get(c, WS_VP, (size_t)n_vtiles * units * 64 * 16, &vp));
+  GMGM_TRY(ws_get(c, WS_NORMS, (size_t)n * 4 + (size_t)w_rows * 12 + 256, &norms));
+  GMGM_TRY(ws_get(c, WS_MISC, 256, &misc));
+  GMGM_TRY(ws_get(c, WS_FALLBACK, (size_t)rows * 8 + 64, &lists));
+  GMGM_TRY(ws_get(c, WS_SCALES, ((size_t)n_vtiles + (size_t)w_rows) * 4 + 64, &scl));
+  StageBufs A;
+  const int nsub = sweep_nsub(TI);
+  GMGM_TRY(stage_buffers(c, WS_WP, WS_CAND, n_wtiles, units, rows, S, nsub, C, &A));
+  A.vp = (const u32x4*)vp;
+  float* vrowmax = (float*)norms;
+  double* wnorm = (double*)((char*)norms + (((size_t)n * 4 + 15) & ~(size_t)15));
+  float* wrowmax = (float*)(wnorm + w_rows);
+  unsigned* vmax_bits = (unsigned*)misc;
+  int* cnt1 = (int*)((char*)misc + 16);
+  int* cnt2 = (int*)((char*)misc + 20);
+  unsigned long long* counters = (unsigned long long*)((char*)misc + 32);
+  int* list1 = (int*)lists;
+  int* list2 = list1 + rows;
+  int* ev = (int*)scl;
+  int* ew = ev + n_vtiles;
+
+  // ---- stage A: prep, repack, sweep in `prec`, certify
+  GMGM_HIP(c, hipMemsetAsync(misc, 0, 64, st));
+  const int prep_blocks = (int)std::min<int64_t>(ceil_div(n, 4), 4096);
+  hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, st, V, psi, n, (int)r, w_lo,
+                     std::min<int64_t>(n, w_lo + w_rows), vrowmax, wnorm, wrowmax, vmax_bits,
+                     c->dev_status);
+  if (prec == P_FP8) {
+    const int64_t m = std::max<int64_t>(n_vtiles, w_rows);
+    hipLaunchKernelGGL(fp8_exps_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, vrowmax,
+                       n, n_vtiles, wrowmax, w_rows, ev, ew);
+  }
+  const int nch = kpad / chunk_elems(prec);
+  launch_repack(prec, [&](auto kern) {
+    const int64_t tv = (int64_t)n_vtiles * 32 * nch, tw = w_rows * nch;
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(tv, 256)), dim3(256), 0, st, V, psi, (int64_t)0,
+                       n, (int64_t)n_vtiles * 32, (int)r, kpad, false, ev, true, (const int*)nullptr,
+                       (const int*)nullptr, (u32x4*)vp);
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(tw, 256)), dim3(256), 0, st, V, psi, w_lo, n,
+                       w_rows, (int)r, kpad, true, ew, false, (const int*)nullptr,
+                       (const int*)nullptr, (u32x4*)A.wp);
+  });
+  SweepArgs sa{};
+  sa.Vp = A.vp;
+  sa.Wp = A.wp;
+  sa.ev = ev;
+  sa.ew = ew;
+  sa.cval = A.cval;
+  sa.cidx = A.cidx;
+  sa.row_list = nullptr;
+  sa.row_count = nullptr;
+  sa.n = n;
+  sa.n_vtiles = n_vtiles;
+  sa.n_wtiles = n_wtiles;
+  sa.row0 = w_lo;
+  sa.row_begin = row_begin;
+  sa.row_end = row_end;
+  sa.S = S;
+  sa.tiles_per_split = tps;
+  hipEvent_t t0 = timing_start(c);
+  sweep<<<dim3((unsigned)gx, (unsigned)S), dim3(SW_THREADS), 0, st>>>(sa);
+  timing_stop(c, t0);
+
+  FinalArgs fa{};
+  fa.cval = A.cval;
+  fa.cidx = A.cidx;
+  fa.V = V;
+  fa.psi = psi;
+  fa.wnorm = wnorm;
+  fa.vmax_bits = vmax_bits;
+  fa.n = n;
+  fa.r = (int)r;
+  fa.k = k;
+  fa.C = C;
+  fa.S = S;
+  fa.nsub = nsub;
+  fa.row_begin = row_begin;
+  fa.rows = rows;
+  fa.w_lo = w_lo;
+  fa.row_list = nullptr;
+  fa.row_count = nullptr;
+  fa.cprec = cprec_for(prec, kpad);
+  fa.col_out = col_out;
+  fa.val_out = val_out;
+  fa.fail_list = list1;
+  fa.fail_count = cnt1;
+  fa.counters = counters;
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, st, fa);
+  hipLaunchKernelGGL(row_ptr_kernel, dim3((unsigned)ceil_div(rows + 1, 256)), dim3(256), 0, st,
+                     row_ptr_out, rows, k);
+  GMGM_HIP(c, hipGetLastError());
+  double flops = 2.0 * (double)w_rows * 32.0 * n_vtiles * kpad;
+
+  // ---- stage B: rows stage A could not certify are re-swept with FP32 operands
+  int h1 = 0, h2 = 0;
+  GMGM_HIP(c, hipMemcpyAsync(&h1, cnt1, 4, hipMemcpyDeviceToHost, st));
+  GMGM_HIP(c, hipStreamSynchronize(st));
+  if (h1 > 0) {
+    const int CB = k <= 12 ? 16 : 32;
+    const int kpadB = kpad_for(P_F32, (int)r);
+    const int unitsB = kpadB / chunk_elems(P_F32) / 2;
+    SweepFn sweepB = pick_sweep(P_F32, kpadB, CB);
+    const int TIB = ti_for(P_F32, CB);
+    const int64_t wtB = ceil_div(h1, 32);
+    const int64_t gxB = ceil_div(wtB, (int64_t)SW_WAVES * TIB);
+    const int SB = pick_splits(gxB, n_vtiles, 64, 1024);
+    const int tpsB = (int)ceil_div(n_vtiles, SB);
+    StageBufs B;
+    const int nsubB = sweep_nsub(TIB);
+    GMGM_TRY(stage_buffers(c, WS_WP2, WS_CAND2, wtB, unitsB, h1, SB, nsubB, CB, &B));
+    if (prec == P_F32 && kpadB == kpad) {
+      B.vp = A.vp;
+    } else {
+      void* vpb;
+      GMGM_TRY(ws_get(c, WS_VP2, (size_t)n_vtiles * unitsB * 64 * 16, &vpb));
+      B.vp = (const u32x4*)vpb;
+      const int64_t tv = (int64_t)n_vtiles * 32 * (kpadB / 4);
+      hipLaunchKernelGGL(repack_kernel<P_F32>, dim3((unsigned)ceil_div(tv, 256)), dim3(256), 0, st, V,
+                         psi, (int64_t)0, n, (int64_t)n_vtiles * 32, (int)r, kpadB, false, ev, true,
+                         (const int*)nullptr, (const int*)nullptr, (u32x4*)vpb);
+    }
+    const int64_t twB = wtB * 32 * (kpadB / 4);
+    hipLaunchKernelGGL(repack_kernel<P_F32>, dim3((unsigned)ceil_div(twB, 256)), dim3(256), 0, st, V,
+                       psi, (int64_t)0, n, wtB * 32, (int)r, kpadB, true, ew, false, (const int*)list1,
+                       (const int*)cnt1, (u32x4*)B.wp);
+    SweepArgs sb = sa;
+    sb.Vp = B.vp;
+    sb.Wp = B.wp;
+    sb.cval = B.cval;
+    sb.cidx = B.cidx;
+    sb.row_list = list1;
+    sb.row_count = cnt1;
+    sb.n_wtiles = (int)wtB;
+    sb.S = SB;
+    sb.tiles_per_split = tpsB;
+    sweepB<<<dim3((unsigned)gxB, (unsigned)SB), dim3(SW_THREADS), 0, st>>>(sb);
+    FinalArgs fb = fa;
+    fb.cval = B.cval;
+    fb.cidx = B.cidx;
+    fb.C = CB;
+    fb.S = SB;
+    fb.nsub = nsubB;
+    fb.row_list = list1;
+    fb.row_count = cnt1;
+    fb.cprec = cprec_for(P_F32, kpadB);
+    fb.fail_list = list2;
+    fb.fail_count = cnt2;
+    fb.counters = counters + 2;    // stage-B candidates are not counted with stage A's
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)ceil_div(h1, 4)), dim3(256), 0, st, fb);
+    GMGM_HIP(c, hipGetLastError());
+    flops += 2.0 * (double)wtB * 32.0 * n_vtiles * 32.0 * kpadB;
+    GMGM_HIP(c, hipMemcpyAsync(&h2, cnt2, 4, hipMemcpyDeviceToHost, st));
+    GMGM_HIP(c, hipStreamSynchronize(st));
+    // ---- stage C: rows still uncertified (exact ties at the boundary, non-finite inputs)
+    if (h2 > 0) {
+      hipLaunchKernelGGL(exact_scan_kernel, dim3((unsigned)std::min(h2, 4096)), dim3(256), 0, st, V,
+                         psi, n, (int)r, k, row_begin, list2, cnt2, col_out, val_out);
+      GMGM_HIP(c, hipGetLastError());
+    }
+  }
+  if (stats) {
+    unsigned long long hc[2];
+    GMGM_HIP(c, hipMemcpyAsync(hc, counters, 16, hipMemcpyDeviceToHost, st));
+    GMGM_HIP(c, hipStreamSynchronize(st));
+    stats->cand_total = (int64_t)hc[0];
+    stats->rows_near_tie = (int64_t)hc[1];
+    stats->rows_fallback = h1;
+    stats->rows_exact = h2;
+    stats->mfma_flops = flops;
+  }
+  return GMGM_OK;
+}

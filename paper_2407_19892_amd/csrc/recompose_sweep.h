@@ -1,0 +1,399 @@
+// MFMA sweep of the fused recomposition + top-k (shared by the per-precision
+// translation units that instantiate it).
+//
+// One workgroup = SW_WAVES waves; wave w keeps W (the psi-scaled rows of Psi it
+// owns, TI tiles of 32 rows) in registers as the MFMA B operand for the whole
+// sweep.  The 32-row tiles of V (the A operand, i.e. 32 columns of Psi) stream
+// through double-buffered LDS, a few tiles per stage, loaded once per
+// workgroup with coalesced 16-byte loads and read by every wave.  After each
+// 32x32 MFMA tile a lane holds 16 values of one row of Psi (the accumulator
+// column is the lane).  Each lane keeps a sorted top-C list (approximate
+// |Psi_ij|, ascending j, ties to smaller j) of the row it owns and tests a
+// whole tile against the list's last entry with one max and one compare;
+// values above it are appended to a per-lane LDS queue that is merged into
+// the list (all lanes in parallel) only when some lane's queue fills.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gmgm_internal.h"
+#include "mfma_util.h"
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+namespace gmgm_rc {
+
+constexpr int INVALID_J = 0x7fffffff;
+constexpr int SW_WAVES = 8;                 // waves per workgroup (2 per SIMD)
+constexpr int SW_THREADS = 64 * SW_WAVES;
+
+struct SweepArgs {
+  const u32x4* Vp;        // repacked V: n_vtiles tiles of UNITS*64 chunks
+  const u32x4* Wp;        // repacked W: one tile per 32 local rows
+  const int* ev;          // FP8: per V tile exponent
+  const int* ew;          // FP8: per local W row exponent
+  float* cval;            // candidates: [slot][split][sublist][C]
+  int* cidx;
+  const int* row_list;    // list mode: local row -> global row (nullptr: contiguous rows)
+  const int* row_count;   // list mode: number of listed rows (device)
+  int64_t n;
+  int n_vtiles;
+  int n_wtiles;           // contiguous mode: W tiles; list mode: capacity in tiles
+  int64_t row0;           // contiguous mode: global row of local row 0
+  int64_t row_begin, row_end;   // contiguous mode: rows whose lists are written
+  int S, tiles_per_split;
+};
+
+template <int PREC>
+__device__ inline v16f mfma_chunk(const u32x4* a, const u32x4* b, v16f acc, int u) {
+  if constexpr (PREC == P_F32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[u][q]), __uint_as_float(b[u][q]),
+                                                acc, 0, 0, 0);
+  } else if constexpr (PREC == P_BF16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a[u]),
+                                                 __builtin_bit_cast(v8bf, b[u]), acc, 0, 0, 0);
+  } else {
+    if ((u & 1) == 0) {
+      v8i av = __builtin_bit_cast(v8i, __builtin_shufflevector(a[u], a[u + 1], 0, 1, 2, 3, 4, 5, 6, 7));
+      v8i bv = __builtin_bit_cast(v8i, __builtin_shufflevector(b[u], b[u + 1], 0, 1, 2, 3, 4, 5, 6, 7));
+      // format 0 = FP8 e4m3 for both operands, unit block scales (E8M0 127 = 2^0)
+      acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
+    }
+  }
+  return acc;
+}
+
+// Insert (v, j) into the descending list (lv, li) of length C; requires v > lv[C-1].
+// Equal values keep their order, so with ascending j per lane ties go to smaller j.
+template <int C>
+__device__ inline void list_insert(float (&lv)[C], int (&li)[C], float v, int j) {
+  bool gt[C];
+#pragma unroll
+  for (int s = 0; s < C; ++s) gt[s] = v > lv[s];
+#pragma unroll
+  for (int s = C - 1; s > 0; --s) {
+    float nv = gt[s - 1] ? lv[s - 1] : (gt[s] ? v : lv[s]);
+    int nj = gt[s - 1] ? li[s - 1] : (gt[s] ? j : li[s]);
+    lv[s] = nv;
+    li[s] = nj;
+  }
+  lv[0] = gt[0] ? v : lv[0];
+  li[0] = gt[0] ? j : li[0];
+}
+
+// Lane halves: after a 32x32 MFMA, lanes l and l + 32 hold the two halves
+// (16 columns each) of the same row.  v_permlane32_swap exchanges the upper
+// half of one register with the lower half of another; it is used to share
+// per-lane scalars between the two halves.
+__device__ inline void swap_halves(float& x, float& y) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+__device__ inline void swap_halves(int& x, int& y) {
+  auto r = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
+  x = (int)r[0];
+  y = (int)r[1];
+}
+
+// With two row tiles per wave ("pair" mode) lane l < 32 owns the list of row
+// l of tile 0 and lane l + 32 the list of row l of tile 1 (whole rows); with
+// one row tile each lane owns the list of its half row.
+__host__ __device__ constexpr bool sweep_pairs(int TI) { return TI == 2; }
+__host__ __device__ constexpr int sweep_nsub(int TI) { return sweep_pairs(TI) ? 1 : 2; }
+// V tiles per LDS stage: about 28 KB per stage buffer.
+__host__ __device__ constexpr int sweep_tps(int UNITS) { return 28 / UNITS > 0 ? 28 / UNITS : 1; }
+constexpr int SW_Q = 8;   // append-queue entries per (list, writer half), in LDS
+
+struct QEntry {
+  float v;
+  int j;
+};
+
+template <int PREC, int UNITS, int TI, int C>
+__global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
+  static_assert(TI == 1 || TI == 2, "one or two row tiles per wave");
+  constexpr bool PAIR = sweep_pairs(TI);
+  constexpr int NSUB = sweep_nsub(TI);
+  constexpr int TPS = sweep_tps(UNITS);
+  constexpr int TILE_U = UNITS * 64;              // chunks per V tile
+  constexpr int STAGE_U = TPS * TILE_U;           // chunks per stage
+  constexpr int PF = (STAGE_U + SW_THREADS - 1) / SW_THREADS;
+  __shared__ u32x4 lds[2][STAGE_U];
+  // queue[wave][owner lane][writer half][entry]
+  __shared__ QEntry queue[SW_WAVES][64][2][SW_Q];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int h = lane >> 5;
+  const int l32 = lane & 31;
+  const bool listed = a.row_list != nullptr;
+  const int nrows_list = listed ? *a.row_count : 0;
+  const int n_wt = listed ? (nrows_list + 31) / 32 : a.n_wtiles;
+  const int wg_t0 = blockIdx.x * SW_WAVES * TI;
+  if (wg_t0 >= n_wt) return;                      // whole workgroup idle (uniform)
+  const int wt0 = wg_t0 + wave * TI;
+  const bool active = wt0 < n_wt;                 // wave-uniform; idle waves still stage V
+
+  u32x4 b[TI][UNITS];
+  int64_t myrow[TI];                              // global row of this lane's values (-1: none)
+  int64_t slot[TI];                               // candidate slot (-1: not written)
+  int ewt[TI];
+#pragma unroll
+  for (int t = 0; t < TI; ++t) {
+    const int wt = wt0 + t;
+    const int64_t w = (int64_t)wt * 32 + l32;
+    ewt[t] = 0;
+    myrow[t] = -1;
+    slot[t] = -1;
+    if (wt < n_wt) {
+#pragma unroll
+      for (int u = 0; u < UNITS; ++u) b[t][u] = a.Wp[((int64_t)wt * UNITS + u) * 64 + lane];
+      if constexpr (PREC == P_FP8) ewt[t] = a.ew[w];
+      if (listed) {
+        if (w < nrows_list) {
+          myrow[t] = a.row_list[w];
+          slot[t] = w;
+        }
+      } else {
+        myrow[t] = a.row0 + w;
+        if (myrow[t] >= a.row_begin && myrow[t] < a.row_end) slot[t] = myrow[t] - a.row_begin;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < UNITS; ++u) b[t][u] = u32x4{0, 0, 0, 0};
+    }
+  }
+  // contiguous mode: the wave's rows are tiles tile0 .. tile0 + TI - 1 of V
+  const int tile0 = (int)(a.row0 >> 5) + wt0;
+
+  // the list this lane owns, and the lists its values go to
+  float lv[C];
+  int li[C];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    lv[s] = -1.0f;
+    li[s] = INVALID_J;
+  }
+  float tau[TI];       // last entry of the list that tile t's values of this lane go to
+  int cnt[TI];         // entries this lane queued for that list
+#pragma unroll
+  for (int t = 0; t < TI; ++t) {
+    tau[t] = -1.0f;
+    cnt[t] = 0;
+  }
+  // owner lane of the list that tile t's values of this lane go to
+  auto owner = [&](int t) { return PAIR ? l32 + 32 * t : lane; };
+
+  // Merge every queue of the wave into its owner's list (all lanes at once),
+  // then refresh the cached thresholds.  Wave-uniform.
+  auto flush = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int c0, c1;
+    if constexpr (PAIR) {
+      c0 = cnt[0];
+      c1 = cnt[TI - 1];
+      swap_halves(c0, c1);       // owner's queues: c0 from writer half 0, c1 from half 1
+    } else {
+      c0 = cnt[0];
+      c1 = 0;
+    }
+    int maxc = max(c0, c1);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) maxc = max(maxc, __shfl_xor(maxc, off, 64));
+    for (int q = 0; q < maxc; ++q) {
+      if (q < c0) {
+        const QEntry e = queue[wave][lane][0][q];
+        if (e.v > lv[C - 1]) list_insert<C>(lv, li, e.v, e.j);
+      }
+      if (PAIR && q < c1) {
+        const QEntry e = queue[wave][lane][1][q];
+        if (e.v > lv[C - 1]) list_insert<C>(lv, li, e.v, e.j);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 0; t < TI; ++t) cnt[t] = 0;
+    if constexpr (PAIR) {
+      float x = lv[C - 1], y = lv[C - 1];
+      swap_halves(x, y);         // x: list of row l32 of tile 0, y: of tile 1
+      tau[0] = x;
+      tau[TI - 1] = y;
+    } else {
+      tau[0] = lv[C - 1];
+    }
+  };
+
+  const int jt0 = blockIdx.y * a.tiles_per_split;
+  const int jt1 = min(a.n_vtiles, jt0 + a.tiles_per_split);
+  const int nst = jt1 > jt0 ? (jt1 - jt0 + TPS - 1) / TPS : 0;
+
+  u32x4 pf[PF];
+  auto load_stage = [&](int st) {
+    const int64_t base = (int64_t)(jt0 + st * TPS) * TILE_U;
+    const int64_t lim = (int64_t)jt1 * TILE_U;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int idx = tid + q * SW_THREADS;
+      const int64_t g = base + idx;
+      pf[q] = (idx < STAGE_U && g < lim) ? a.Vp[g] : u32x4{0, 0, 0, 0};
+    }
+  };
+  auto store_stage = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int idx = tid + q * SW_THREADS;
+      if (idx < STAGE_U) lds[buf][idx] = pf[q];
+    }
+  };
+
+  if (nst > 0) {
+    load_stage(0);
+    store_stage(0);
+  }
+  // All prologue loads (the B operands above all) have landed: without this
+  // the waitcnt analysis cannot prove it inside the loop and makes the MFMAs
+  // wait for the next stage's prefetch.
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    if (st + 1 < nst) load_stage(st + 1);        // global loads in flight during the MFMAs
+    if (active) {
+#pragma unroll 1
+      for (int tt = 0; tt < TPS; ++tt) {
+        const int jt = jt0 + st * TPS + tt;
+        if (jt >= jt1) break;
+        u32x4 av[UNITS];
+#pragma unroll
+        for (int u = 0; u < UNITS; ++u) av[u] = lds[st & 1][tt * TILE_U + u * 64 + lane];
+        v16f acc[TI];
+#pragma unroll
+        for (int t = 0; t < TI; ++t)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[t][v] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < UNITS; ++u)
+#pragma unroll
+          for (int t = 0; t < TI; ++t) acc[t] = mfma_chunk<PREC>(av, b[t], acc[t], u);
+
+        const int64_t j0 = (int64_t)jt * 32;
+        bool masked = j0 + 32 > a.n;               // wave-uniform
+        if (listed) {
+          bool diag = false;
+#pragma unroll
+          for (int t = 0; t < TI; ++t) diag |= myrow[t] >= 0 && (myrow[t] >> 5) == jt;
+          masked = masked || __ballot(diag) != 0;
+        } else {
+          masked = masked || (jt >= tile0 && jt < tile0 + TI);
+        }
+        int evt = 0;
+        if constexpr (PREC == P_FP8) evt = a.ev[jt];
+
+        // fast path: one max per (row tile) and one compare with the cached threshold
+        float thr[TI], m[TI];
+        bool pass[TI], any = false;
+#pragma unroll
+        for (int t = 0; t < TI; ++t) {
+          float mm;
+          if (masked) {
+            mm = -1.0f;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int64_t j = j0 + acc_row(v, h);
+              mm = fmaxf(mm, (j < a.n && j != myrow[t]) ? fabsf(acc[t][v]) : -1.0f);
+            }
+          } else {
+            mm = fabsf(acc[t][0]);
+#pragma unroll
+            for (int v = 1; v < 16; ++v) mm = fmaxf(mm, fabsf(acc[t][v]));
+          }
+          m[t] = mm;
+          thr[t] = tau[t];
+          if constexpr (PREC == P_FP8) thr[t] = __builtin_ldexpf(thr[t], -(ewt[t] + evt));
+          pass[t] = mm > thr[t];
+          any |= pass[t];
+        }
+        if (__ballot(any)) {
+#pragma unroll
+          for (int t = 0; t < TI; ++t) {
+            if (!__ballot(pass[t])) continue;
+            // groups of 4 values (4 consecutive columns); queue the values above
+            // the threshold of the groups that have any, without branches per value
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              bool ok[4];
+              float x[4];
+              float gm = -1.0f;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int64_t j = j0 + acc_row(4 * g + e, h);
+                x[e] = fabsf(acc[t][4 * g + e]);
+                ok[e] = !masked || (j < a.n && j != myrow[t]);
+                gm = fmaxf(gm, ok[e] ? x[e] : -1.0f);
+              }
+              if (!__ballot(gm > thr[t])) continue;
+              if (__ballot(cnt[t] > SW_Q - 4)) {
+                flush();
+#pragma unroll
+                for (int t2 = 0; t2 < TI; ++t2) {
+                  thr[t2] = tau[t2];
+                  if constexpr (PREC == P_FP8) thr[t2] = __builtin_ldexpf(thr[t2], -(ewt[t2] + evt));
+                }
+              }
+              QEntry* qp = &queue[wave][owner(t)][PAIR ? h : 0][0];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const bool take = ok[e] && x[e] > thr[t];
+                float xv = x[e];
+                if constexpr (PREC == P_FP8) xv = __builtin_ldexpf(xv, ewt[t] + evt);
+                qp[cnt[t]] = QEntry{xv, (int)(j0 + acc_row(4 * g + e, h))};   // kept only if taken
+                cnt[t] += take ? 1 : 0;
+              }
+            }
+          }
+        }
+      }
+    }
+    if (st + 1 < nst) store_stage((st + 1) & 1);
+    __syncthreads();
+  }
+
+  if (!active) return;
+  flush();
+  // the list of this lane: row l32 of tile h (pairs) or this lane's half row
+  const int to = PAIR ? h : 0;
+  if (slot[to] >= 0) {
+    const int sub = PAIR ? 0 : h;
+    const int64_t base = ((slot[to] * a.S + blockIdx.y) * NSUB + sub) * C;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      a.cval[base + s] = lv[s];
+      a.cidx[base + s] = li[s];
+    }
+  }
+}
+
+typedef void (*SweepFn)(SweepArgs);
+
+// Row tiles per wave: two for the short BF16 / FP8 operands (each lane then
+// owns one full row), one for FP32 operands (lanes keep half rows); this is
+// the register budget of the B operands and lists at 2 waves per SIMD.
+__host__ __device__ constexpr int ti_for(int prec, int C) {
+  return (prec != P_F32) ? 2 : 1;
+}
+
+// One translation unit per (precision, list length) keeps the build parallel.
+SweepFn pick_sweep_f32_c16(int kpad);
+SweepFn pick_sweep_f32_c32(int kpad);
+SweepFn pick_sweep_bf16_c16(int kpad);
+SweepFn pick_sweep_bf16_c32(int kpad);
+SweepFn pick_sweep_fp8_c16(int kpad);
+SweepFn pick_sweep_fp8_c32(int kpad);
+
+}  // namespace gmgm_rc
