@@ -127,6 +127,55 @@ gmgm_status gmgm_recompose_topk(gmgm_ctx_t ctx, int64_t n, int64_t r, const floa
                                 int64_t* row_ptr_out, int32_t* col_out, float* val_out,
                                 gmgm_topk_stats* stats);
 
+/* Result of one gmgm_solve_eigs call. */
+typedef struct {
+  int32_t iterations;       /* Newton iterations taken */
+  int32_t converged;        /* 1 if the KKT residual reached tol */
+  int32_t n_flat;           /* number of zero-slope shift directions fixed by the gauge rule */
+  int32_t reserved;
+  double kkt;               /* final scaled KKT residual */
+  int64_t n_pinned[8];      /* per axis: eigenvalues that end at their bound eps_l */
+  double eps[8];            /* per axis: the bound used */
+} gmgm_solve_info;
+
+/*
+ * Eigenvalue maximum-likelihood estimate (Algorithm 1's eigenvalue loop;
+ * eigenvalue-gradient Proposition; Existence lemma).  With the eigenvectors
+ * fixed by Theorem 1, minimise over lambda_l,i >= eps_l
+ *   NLL = 1/2 [ sum_l sum_i E_l,i lambda_l,i
+ *               - sum_{modalities (a,b)} sum_{i<r_a, j<r_b} log(lambda_a,i + lambda_b,j) ].
+ * Projected Newton (Schur complement on a minimum-rank vertex cover of the
+ * modality graph, Cholesky of that system on the device), Armijo search, FP64
+ * throughout, deterministic reductions.  Start: Algorithm 1's 1/E, or `warm`.
+ * Shift directions along which the NLL is flat (every modality's two axes
+ * shifted by +c and -c with equal traces) are fixed to the gauge of 1/E.
+ *
+ *   n_axes       2..8 axes.
+ *   ranks        host, n_axes retained ranks r_l >= 1.
+ *   E            host array of n_axes device pointers; E[l] holds r_l positive
+ *                finite FP64 eigenvalues of S_l (any order).
+ *   n_mod        1 .. n_axes (n_axes - 1) / 2 modalities.
+ *   modalities   host, 2 * n_mod axis indices (a, b), a != b, pairs distinct;
+ *                every axis must belong to one.
+ *   eps          host, n_axes positive bounds, or NULL for 1e-10 / max_i E_l,i.
+ *   warm         host array of n_axes device pointers (finite starting
+ *                eigenvalues; moved to the gauge, then clipped to the box), or NULL.
+ *   tol          stop when max over coordinates of |g| / (E/2) (free) or
+ *                max(0, -g) / (E/2) (at the bound) is <= tol; 1e-12 is typical.
+ *   max_iter     Newton iteration limit (>= 0).
+ *   lambda_out   host array of n_axes device pointers, r_l FP64 each (written).
+ *   info         host pointer or NULL.
+ * The Schur system (sum of the hub axes' ranks) is limited to 2048 unknowns.
+ * Synchronises (every iteration reads scalars back).  Returns GMGM_E_NOCONV
+ * (outputs written, info filled) when tol is not reached in max_iter
+ * iterations or the line search stalls; GMGM_E_DOMAIN for non-positive or
+ * non-finite E, non-finite warm starts or bad eps.
+ */
+gmgm_status gmgm_solve_eigs(gmgm_ctx_t ctx, int32_t n_axes, const int64_t* ranks,
+                            const double* const* E, int32_t n_mod, const int32_t* modalities,
+                            const double* eps, const double* const* warm, double tol,
+                            int32_t max_iter, double* const* lambda_out, gmgm_solve_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,12 @@ class TopkStats(ctypes.Structure):
                 ("mfma_flops", ctypes.c_double)]
 
 
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("n_flat", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kkt", ctypes.c_double),
+                ("n_pinned", ctypes.c_int64 * 8), ("eps", ctypes.c_double * 8)]
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
@@ -51,6 +57,10 @@ SIGNATURES = {
     "gmgm_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "gmgm_recompose_topk": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, _I64, _I32, ctypes.c_int,
                                            _I32, _P, _P, _P, ctypes.POINTER(TopkStats)]),
+    "gmgm_solve_eigs": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_P), _I32,
+                                       ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(_P), ctypes.c_double, _I32, ctypes.POINTER(_P),
+                                       ctypes.POINTER(SolveInfo)]),
 }
 
 
@@ -164,3 +174,47 @@ def recompose_topk(V, psi, k: int, prec: str = "bf16", row_begin: int = 0, row_e
               "rows_near_tie": st.rows_near_tie, "rows_exact": st.rows_exact,
               "mfma_flops": st.mfma_flops}
     return TopkResult(rp, col, val, sd)
+
+
+@dataclass
+class SolveResult:
+    lam: list
+    info: dict
+
+
+def solve_eigs(E, modalities, eps=None, warm=None, tol: float = 1e-12, max_iter: int = 200,
+               raise_on_noconv: bool = True) -> SolveResult:
+    """Eigenvalue MLE over the box lambda >= eps (see gmgm_solve_eigs).
+
+    E: list of FP64 device tensors (one per axis); modalities: list of (a, b)
+    axis pairs; warm: optional list of FP64 device tensors.  Returns the
+    per-axis eigenvalues (new device tensors) and the solve record."""
+    import torch
+    L = len(E)
+    for e in E:
+        if not (e.is_cuda and e.dtype == torch.float64 and e.dim() == 1 and e.is_contiguous()):
+            raise TypeError("every E must be a contiguous 1-D float64 device tensor")
+    if warm is not None:
+        if len(warm) != L:
+            raise ValueError("warm needs one tensor per axis")
+        for w, e in zip(warm, E):
+            if not (w.is_cuda and w.dtype == torch.float64 and w.is_contiguous() and w.numel() == e.numel()):
+                raise TypeError("warm tensors must be contiguous float64 device tensors shaped like E")
+    out = [torch.empty_like(e) for e in E]
+    ranks = (_I64 * L)(*[e.numel() for e in E])
+    eptr = (_P * L)(*[e.data_ptr() for e in E])
+    optr = (_P * L)(*[o.data_ptr() for o in out])
+    flat = [int(x) for ab in modalities for x in ab]
+    mods = (_I32 * len(flat))(*flat)
+    epsa = (ctypes.c_double * L)(*eps) if eps is not None else None
+    wptr = (_P * L)(*[w.data_ptr() for w in warm]) if warm is not None else None
+    info = SolveInfo()
+    c = context(E[0].device.index)
+    st = load().gmgm_solve_eigs(c, L, ranks, eptr, len(modalities), mods, epsa, wptr, float(tol),
+                                int(max_iter), optr, ctypes.byref(info))
+    d = {"iterations": info.iterations, "converged": bool(info.converged), "n_flat": info.n_flat,
+         "kkt": info.kkt, "n_pinned": list(info.n_pinned[:L]), "eps": list(info.eps[:L])}
+    if st == 4 and not raise_on_noconv:
+        return SolveResult(out, d)
+    _check(c, st)
+    return SolveResult(out, d)

@@ -1,0 +1,762 @@
+// Eigenvalue maximum-likelihood estimate on the GPU (FP64).
+//
+// With Theorem 1's eigenvectors fixed, the model equation's negative
+// log-likelihood of modalities gamma = (a, b) in the eigenvalues is
+//   NLL = 1/2 [ sum_l sum_i E_l,i lam_l,i - sum_gamma sum_{i,j} log(lam_a,i + lam_b,j) ],
+// its gradient (eigenvalue-gradient Proposition)
+//   dNLL/dlam_l,i = 1/2 ( E_l,i - sum_{partners m} sum_j 1/(lam_l,i + lam_m,j) ),
+// minimised over the Existence lemma's box lam_l,i >= eps_l.
+//
+// Method: projected Newton for bound constraints with a vanishing
+// Levenberg-Marquardt damping rho = min(1e-2, KKT residual) and an Armijo
+// search along the projection arc.  The host drives the iteration; every
+// arithmetic step runs in the kernels below.  The Newton system is solved by
+// a Schur complement: "hub" axes (a minimum-rank vertex cover of the modality
+// graph) stay, the other axes have diagonal Hessian blocks and are
+// eliminated; the hub system is factored by a one-workgroup Cholesky.
+// Directions that shift whole axes with zero NLL slope (balanced problems)
+// are projected out of every step, and the result is normalised to the gauge
+// of the start 1/E.  Reductions are deterministic (fixed order, compensated).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "gmgm_internal.h"
+
+namespace gmgm_sv {
+
+constexpr int RED_THREADS = 1024;
+constexpr int MAX_AXES = 8;
+constexpr int MAX_HUB = 2048;
+
+__device__ inline void neumaier(double& s, double& c, double x) {
+  const double t = s + x;
+  c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-order sum over a block of RED_THREADS threads (result valid in thread 0).
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < RED_THREADS / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// For every i < nx: s1[i] (+)= sum_j 1/(x_i + y_j), s2[i] (+)= sum_j (x_i + y_j)^-2 and,
+// when lg is given, lg[i] (+)= sum_j log(x_i + y_j).  One wave per i.
+__global__ void __launch_bounds__(256) pair_sums_kernel(const double* __restrict__ x, int nx,
+                                                        const double* __restrict__ y, int ny,
+                                                        double* __restrict__ s1,
+                                                        double* __restrict__ s2,
+                                                        double* __restrict__ lg, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nx) return;
+  const double xi = x[i];
+  double a1 = 0, c1 = 0, a2 = 0, c2 = 0, a3 = 0, c3 = 0;
+  for (int j = lane; j < ny; j += 64) {
+    const double s = xi + y[j];
+    const double r = 1.0 / s;
+    neumaier(a1, c1, r);
+    neumaier(a2, c2, r * r);
+    if (lg) neumaier(a3, c3, log(s));
+  }
+  a1 = wave_sum(a1) + wave_sum(c1);
+  a2 = wave_sum(a2) + wave_sum(c2);
+  if (lg) a3 = wave_sum(a3) + wave_sum(c3);
+  if (lane == 0) {
+    if (s1) s1[i] = accumulate ? s1[i] + a1 : a1;
+    if (s2) s2[i] = accumulate ? s2[i] + a2 : a2;
+    if (lg) lg[i] = accumulate ? lg[i] + a3 : a3;
+  }
+}
+
+// g = (E - s1)/2, h = s2/2, the active set and each coordinate's KKT term:
+// |g| / (E/2) when free, max(0, -g) / (E/2) at the bound.
+__global__ void assemble_kernel(const double* __restrict__ E, const double* __restrict__ lam,
+                                const double* __restrict__ s1, const double* __restrict__ s2,
+                                double eps, int n, double* __restrict__ g, double* __restrict__ h,
+                                int* __restrict__ active, double* __restrict__ kkt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double gi = 0.5 * (E[i] - s1[i]);
+  const double hi = 0.5 * s2[i];
+  g[i] = gi;
+  h[i] = hi;
+  // coordinates within a diagonal-Newton step of their bound that want to go down
+  const double reach = fmin(1e-3 * lam[i], gi / hi);
+  active[i] = (lam[i] - eps <= reach) && (gi > 0.0);
+  const bool at = lam[i] <= eps * (1.0 + 1e-12);
+  kkt[i] = (at ? fmax(0.0, -gi) : fabs(gi)) / (0.5 * E[i]);
+}
+
+// Schur complement of a leaf axis m against hub axes K1 (rows) and K2 (columns):
+//   S[K1_i][K2_k] -= sum_{free j} B1[i][j] B2[k][j] / ((1+rho) h_m[j]),
+//   B[i][j] = 1/2 (x_i + y_j)^-2,
+// and, when with_rhs, rhs[K1_i] += sum_{free j} B1[i][j] g_m[j] / ((1+rho) h_m[j]).
+// A 16 x 16 tile of S per workgroup.
+__global__ void __launch_bounds__(256) schur_leaf_kernel(
+    const double* __restrict__ x1, int n1, int off1, const double* __restrict__ x2, int n2, int off2,
+    const double* __restrict__ ym, int nm, const int* __restrict__ act_m,
+    const double* __restrict__ hm, const double* __restrict__ gm, double damp,
+    double* __restrict__ S, int ldS, double* __restrict__ rhs, int with_rhs) {
+  __shared__ double b1[16][65], b2[16][65], w[64], wg[64];
+  const int ti = threadIdx.x >> 4, tk = threadIdx.x & 15;
+  const int i = blockIdx.y * 16 + ti, k = blockIdx.x * 16 + tk;
+  double acc = 0.0, racc = 0.0;
+  for (int j0 = 0; j0 < nm; j0 += 64) {
+    for (int q = threadIdx.x; q < 16 * 64; q += 256) {
+      const int rr = q >> 6, jj = q & 63, j = j0 + jj;
+      const int ir = blockIdx.y * 16 + rr, kr = blockIdx.x * 16 + rr;
+      double v1 = 0.0, v2 = 0.0;
+      if (j < nm && !act_m[j]) {
+        if (ir < n1) {
+          const double s = x1[ir] + ym[j];
+          v1 = 0.5 / (s * s);
+        }
+        if (kr < n2) {
+          const double s = x2[kr] + ym[j];
+          v2 = 0.5 / (s * s);
+        }
+      }
+      b1[rr][jj] = v1;
+      b2[rr][jj] = v2;
+    }
+    if (threadIdx.x < 64) {
+      const int j = j0 + threadIdx.x;
+      const bool fr = j < nm && !act_m[j];
+      w[threadIdx.x] = fr ? 1.0 / (damp * hm[j]) : 0.0;
+      wg[threadIdx.x] = fr ? gm[j] / (damp * hm[j]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int jj = 0; jj < 64; ++jj) acc += b1[ti][jj] * b2[tk][jj] * w[jj];
+    if (with_rhs && blockIdx.x == 0 && tk == 0)
+      for (int jj = 0; jj < 64; ++jj) racc += b1[ti][jj] * wg[jj];
+    __syncthreads();
+  }
+  if (i < n1 && k < n2) S[(size_t)(off1 + i) * ldS + off2 + k] -= acc;
+  if (with_rhs && blockIdx.x == 0 && tk == 0 && i < n1) rhs[off1 + i] += racc;
+}
+
+// Cross block between hub axes K1 (rows) and K2 (columns): S[K1][K2] += B, S[K2][K1] += B^T.
+__global__ void schur_cross_kernel(const double* __restrict__ x1, int n1, int off1,
+                                   const double* __restrict__ x2, int n2, int off2,
+                                   double* __restrict__ S, int ldS) {
+  const int i = blockIdx.y * 16 + (threadIdx.x >> 4), k = blockIdx.x * 16 + (threadIdx.x & 15);
+  if (i >= n1 || k >= n2) return;
+  const double s = x1[i] + x2[k];
+  const double b = 0.5 / (s * s);
+  S[(size_t)(off1 + i) * ldS + off2 + k] += b;
+  S[(size_t)(off2 + k) * ldS + off1 + i] += b;
+}
+
+// Diagonal (1+rho) h and right-hand side -g of a hub axis; copies its activity flags
+// into hub order.
+__global__ void schur_diag_kernel(const double* __restrict__ h, const double* __restrict__ g,
+                                  const int* __restrict__ act, int n, int off, double damp,
+                                  double* __restrict__ S, int ldS, double* __restrict__ rhs,
+                                  int* __restrict__ act_hub) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  S[(size_t)(off + i) * ldS + off + i] += damp * h[i];
+  rhs[off + i] = -g[i];
+  act_hub[off + i] = act[i];
+}
+
+// Active hub coordinates: identity row and column, zero right-hand side.
+__global__ void schur_pin_kernel(const int* __restrict__ act_hub, int nS, double* __restrict__ S,
+                                 double* __restrict__ rhs) {
+  const int i = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nS) return;
+  if (act_hub[i] || act_hub[k]) S[(size_t)i * nS + k] = (i == k) ? 1.0 : 0.0;
+  if (k == 0 && act_hub[i]) rhs[i] = 0.0;
+}
+
+// Cholesky factorisation (lower, in place) and solve of the SPD system S x = b,
+// row-major n x n, one workgroup.  *bad = 1 if a pivot is not positive.
+__global__ void __launch_bounds__(1024) cholesky_solve_kernel(double* __restrict__ S, int n,
+                                                              double* __restrict__ b,
+                                                              int* __restrict__ bad) {
+  __shared__ double piv;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int c = 0; c < n; ++c) {
+    if (tid == 0) {
+      const double d = S[(size_t)c * n + c];
+      if (!(d > 0.0)) *bad = 1;
+      piv = sqrt(fmax(d, 1e-300));
+      S[(size_t)c * n + c] = piv;
+    }
+    __syncthreads();
+    for (int r = c + 1 + tid; r < n; r += nt) S[(size_t)r * n + c] /= piv;
+    __syncthreads();
+    // trailing update of the lower triangle, 32 threads per row
+    for (int r = c + 1 + tid / 32; r < n; r += nt / 32) {
+      const double lr = S[(size_t)r * n + c];
+      for (int k = c + 1 + (tid & 31); k <= r; k += 32) S[(size_t)r * n + k] -= lr * S[(size_t)k * n + c];
+    }
+    __syncthreads();
+  }
+  for (int c = 0; c < n; ++c) {          // L y = b
+    if (tid == 0) b[c] /= S[(size_t)c * n + c];
+    __syncthreads();
+    for (int r = c + 1 + tid; r < n; r += nt) b[r] -= S[(size_t)r * n + c] * b[c];
+    __syncthreads();
+  }
+  for (int c = n - 1; c >= 0; --c) {     // L^T x = y
+    if (tid == 0) b[c] /= S[(size_t)c * n + c];
+    __syncthreads();
+    for (int r = tid; r < c; r += nt) b[r] -= S[(size_t)c * n + r] * b[c];
+    __syncthreads();
+  }
+}
+
+// Newton step of a hub axis: the Schur solution on free coordinates, -g/h on active ones.
+__global__ void hub_step_kernel(const double* __restrict__ x, const double* __restrict__ g,
+                                const double* __restrict__ h, const int* __restrict__ act, int n,
+                                double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  d[i] = act[i] ? -g[i] / h[i] : x[i];
+}
+
+// acc[j] += sum_{free hub i} B[i][j] d_K[i] for a leaf axis (one wave per j).
+__global__ void __launch_bounds__(256) leaf_partner_kernel(const double* __restrict__ ym, int nm,
+                                                           const double* __restrict__ xK, int nK,
+                                                           const int* __restrict__ actK,
+                                                           const double* __restrict__ dK,
+                                                           double* __restrict__ acc) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nm) return;
+  double s = 0.0;
+  for (int i = lane; i < nK; i += 64) {
+    if (actK[i]) continue;
+    const double t = xK[i] + ym[j];
+    s += 0.5 / (t * t) * dK[i];
+  }
+  s = wave_sum(s);
+  if (lane == 0) acc[j] += s;
+}
+
+__global__ void leaf_step_kernel(const double* __restrict__ g, const double* __restrict__ h,
+                                 const int* __restrict__ act, const double* __restrict__ acc,
+                                 int n, double damp, double* __restrict__ d) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  d[j] = act[j] ? -g[j] / h[j] : (-g[j] - acc[j]) / (damp * h[j]);
+}
+
+// *out = sum_i a[i] * (b ? b[i] : 1)  (one workgroup, fixed order)
+__global__ void __launch_bounds__(RED_THREADS) dot_kernel(const double* __restrict__ a,
+                                                          const double* __restrict__ b, int n,
+                                                          double* __restrict__ out) {
+  __shared__ double red[RED_THREADS / 64];
+  double s = 0, c = 0;
+  for (int i = threadIdx.x; i < n; i += RED_THREADS) neumaier(s, c, b ? a[i] * b[i] : a[i]);
+  const double t = block_sum(s + c, red);
+  if (threadIdx.x == 0) *out = t;
+}
+
+// *out = max_i a[i]  (one workgroup)
+__global__ void __launch_bounds__(RED_THREADS) max_kernel(const double* __restrict__ a, int n,
+                                                          double* __restrict__ out) {
+  __shared__ double red[RED_THREADS / 64];
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < n; i += RED_THREADS) m = fmax(m, a[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < RED_THREADS / 64; ++w) r = fmax(r, red[w]);
+    *out = r;
+  }
+}
+
+// Trial point t = max(x + alpha d, eps) of one axis.
+__global__ void trial_kernel(const double* __restrict__ x, const double* __restrict__ d, int n,
+                             double alpha, double eps, double* __restrict__ t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = fmax(x[i] + alpha * d[i], eps);
+}
+
+// Armijo prediction: alpha sum_free g d + sum_active g (t - x)   (one workgroup)
+__global__ void __launch_bounds__(RED_THREADS) pred_kernel(
+    const double* __restrict__ g, const double* __restrict__ d, const double* __restrict__ x,
+    const double* __restrict__ t, const int* __restrict__ act, int n, double alpha,
+    double* __restrict__ out) {
+  __shared__ double red[RED_THREADS / 64];
+  double s = 0, c = 0;
+  for (int i = threadIdx.x; i < n; i += RED_THREADS)
+    neumaier(s, c, act[i] ? g[i] * (t[i] - x[i]) : alpha * g[i] * d[i]);
+  const double v = block_sum(s + c, red);
+  if (threadIdx.x == 0) *out = v;
+}
+
+__global__ void add_const_kernel(double* __restrict__ x, int n, double a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += a;
+}
+
+// Start point: the warm start, or Algorithm 1's 1/E; flags non-positive or non-finite
+// E (1) and a non-finite warm start (2).
+__global__ void init_kernel(const double* __restrict__ E, const double* __restrict__ warm, int n,
+                            double* __restrict__ lam, int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double e = E[i];
+  if (!(e > 0.0) || !isfinite(e)) atomicMax(bad, 1);
+  const double v = warm ? warm[i] : 1.0 / e;
+  if (warm && !isfinite(v)) atomicMax(bad, 2);
+  lam[i] = v;
+}
+
+__global__ void clip_kernel(double* __restrict__ lam, double eps, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) lam[i] = fmax(lam[i], eps);
+}
+
+__global__ void __launch_bounds__(RED_THREADS) count_pinned_kernel(const double* __restrict__ lam,
+                                                                   double eps, int n,
+                                                                   double* __restrict__ out) {
+  __shared__ double red[RED_THREADS / 64];
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += RED_THREADS) s += lam[i] <= eps * (1.0 + 1e-12) ? 1.0 : 0.0;
+  const double v = block_sum(s, red);
+  if (threadIdx.x == 0) *out = v;
+}
+
+inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// ------------------------------------------------------------------ host side
+struct Axis {
+  int r = 0;
+  size_t off = 0;   // offset in the concatenated coordinate vectors
+  double eps = 0;
+  double trace = 0;
+};
+
+// Minimum total-rank vertex cover of the modality graph (exhaustive; at most 8 axes).
+std::vector<int> hub_axes(const std::vector<Axis>& ax, const std::vector<std::pair<int, int>>& mods) {
+  const int L = (int)ax.size();
+  std::vector<int> best;
+  long bestw = -1;
+  for (int mask = 0; mask < (1 << L); ++mask) {
+    bool cover = true;
+    for (auto& m : mods) cover = cover && (((mask >> m.first) & 1) || ((mask >> m.second) & 1));
+    if (!cover) continue;
+    long w = 0;
+    for (int l = 0; l < L; ++l)
+      if ((mask >> l) & 1) w += ax[l].r;
+    if (bestw < 0 || w < bestw) {
+      bestw = w;
+      best.clear();
+      for (int l = 0; l < L; ++l)
+        if ((mask >> l) & 1) best.push_back(l);
+    }
+  }
+  return best;
+}
+
+// Axis shifts c (c_a + c_b = 0 for every modality) along which the NLL slope
+// 1/2 sum_l c_l tr_l vanishes; orthonormal in the metric sum_l r_l c_l c'_l.
+std::vector<std::vector<double>> flat_directions(const std::vector<Axis>& ax,
+                                                 const std::vector<std::pair<int, int>>& mods) {
+  const int L = (int)ax.size();
+  std::vector<std::vector<double>> M(mods.size(), std::vector<double>(L, 0.0));
+  for (size_t t = 0; t < mods.size(); ++t) M[t][mods[t].first] = M[t][mods[t].second] = 1.0;
+  // reduced row echelon form of the incidence matrix; its null space spans the shifts
+  std::vector<int> pivcol;
+  int row = 0;
+  for (int c = 0; c < L && row < (int)M.size(); ++c) {
+    int p = -1;
+    for (int r2 = row; r2 < (int)M.size(); ++r2)
+      if (std::fabs(M[r2][c]) > 1e-12) {
+        p = r2;
+        break;
+      }
+    if (p < 0) continue;
+    std::swap(M[row], M[p]);
+    const double dv = M[row][c];
+    for (auto& v : M[row]) v /= dv;
+    for (int r2 = 0; r2 < (int)M.size(); ++r2)
+      if (r2 != row && M[r2][c] != 0.0) {
+        const double f = M[r2][c];
+        for (int c2 = 0; c2 < L; ++c2) M[r2][c2] -= f * M[row][c2];
+      }
+    pivcol.push_back(c);
+    row++;
+  }
+  std::vector<std::vector<double>> flats;
+  for (int c = 0; c < L; ++c) {
+    if (std::find(pivcol.begin(), pivcol.end(), c) != pivcol.end()) continue;
+    std::vector<double> v(L, 0.0);
+    v[c] = 1.0;
+    for (size_t r2 = 0; r2 < pivcol.size(); ++r2) v[pivcol[r2]] = -M[r2][c];
+    double slope = 0, scale = 0;
+    for (int l = 0; l < L; ++l) {
+      slope += v[l] * ax[l].trace;
+      scale += std::fabs(v[l]) * ax[l].trace;
+    }
+    if (std::fabs(slope) > 1e-12 * scale) continue;
+    for (auto& q : flats) {
+      double pr = 0;
+      for (int l = 0; l < L; ++l) pr += ax[l].r * v[l] * q[l];
+      for (int l = 0; l < L; ++l) v[l] -= pr * q[l];
+    }
+    double nrm = 0;
+    for (int l = 0; l < L; ++l) nrm += ax[l].r * v[l] * v[l];
+    nrm = std::sqrt(nrm);
+    if (nrm > 1e-12) {
+      for (auto& e : v) e /= nrm;
+      flats.push_back(v);
+    }
+  }
+  return flats;
+}
+
+struct Solver {
+  gmgm_ctx* c = nullptr;
+  hipStream_t st = nullptr;
+  int L = 0;
+  std::vector<Axis> ax;
+  std::vector<std::pair<int, int>> mods;
+  std::vector<int> hub, is_hub;
+  std::vector<size_t> hoff;
+  size_t T = 0, nS = 0;
+  double *lam, *trial, *Ec, *s1, *s2, *lg, *g, *h, *d, *acc, *kkt, *S, *rhs, *scal;
+  int *act, *act_hub, *flag;
+
+  gmgm_status fetch(double* host, const double* dev, int count) {
+    GMGM_HIP(c, hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    GMGM_HIP(c, hipStreamSynchronize(st));
+    return GMGM_OK;
+  }
+
+  // sum_l cdir_l sum_i v_l,i
+  gmgm_status gauge_value(const double* v, const std::vector<double>& cdir, double* out) {
+    int q = 0;
+    for (int l = 0; l < L; ++l)
+      if (cdir[l] != 0.0)
+        hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, v + ax[l].off,
+                           (const double*)nullptr, ax[l].r, scal + q++);
+    double sums[MAX_AXES];
+    GMGM_TRY(fetch(sums, scal, q));
+    *out = 0;
+    q = 0;
+    for (int l = 0; l < L; ++l)
+      if (cdir[l] != 0.0) *out += cdir[l] * sums[q++];
+    return GMGM_OK;
+  }
+
+  // v += t * cdir (axis-wise constant shift)
+  void shift(double* v, const std::vector<double>& cdir, double t) {
+    for (int l = 0; l < L; ++l)
+      if (cdir[l] != 0.0)
+        hipLaunchKernelGGL(add_const_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, v + ax[l].off,
+                           ax[l].r, t * cdir[l]);
+  }
+
+  // NLL(x) = 1/2 (sum E x - sum log); each modality's log terms counted once.
+  gmgm_status nll(const double* x, double* out) {
+    for (int l = 0; l < L; ++l) {
+      int first = 1;
+      for (auto& m : mods)
+        if (m.first == l) {
+          hipLaunchKernelGGL(pair_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off,
+                             ax[l].r, x + ax[m.second].off, ax[m.second].r, (double*)nullptr,
+                             (double*)nullptr, lg + ax[l].off, first ? 0 : 1);
+          first = 0;
+        }
+      if (first) GMGM_HIP(c, hipMemsetAsync(lg + ax[l].off, 0, ax[l].r * sizeof(double), st));
+    }
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, scal);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, lg, (const double*)nullptr,
+                       (int)T, scal + 1);
+    double v[2];
+    GMGM_TRY(fetch(v, scal, 2));
+    *out = 0.5 * (v[0] - v[1]);
+    return GMGM_OK;
+  }
+
+  // g, h, the active set and the KKT residual at x.
+  gmgm_status gradient(const double* x, double* kres) {
+    for (int l = 0; l < L; ++l) {
+      int first = 1;
+      for (auto& m : mods) {
+        const int other = m.first == l ? m.second : m.second == l ? m.first : -1;
+        if (other < 0) continue;
+        hipLaunchKernelGGL(pair_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off,
+                           ax[l].r, x + ax[other].off, ax[other].r, s1 + ax[l].off, s2 + ax[l].off,
+                           (double*)nullptr, first ? 0 : 1);
+        first = 0;
+      }
+      hipLaunchKernelGGL(assemble_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, Ec + ax[l].off,
+                         x + ax[l].off, s1 + ax[l].off, s2 + ax[l].off, ax[l].eps, ax[l].r,
+                         g + ax[l].off, h + ax[l].off, act + ax[l].off, kkt + ax[l].off);
+    }
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(RED_THREADS), 0, st, kkt, (int)T, scal);
+    return fetch(kres, scal, 1);
+  }
+
+  // Damped projected-Newton direction d at lam (g, h and act current).
+  gmgm_status direction(double rho) {
+    const double damp = 1.0 + rho;
+    GMGM_HIP(c, hipMemsetAsync(S, 0, nS * nS * sizeof(double), st));
+    for (int l : hub)
+      hipLaunchKernelGGL(schur_diag_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, h + ax[l].off,
+                         g + ax[l].off, act + ax[l].off, ax[l].r, (int)hoff[l], damp, S, (int)nS, rhs,
+                         act_hub);
+    for (auto& m : mods)
+      if (is_hub[m.first] && is_hub[m.second]) {
+        const int a = m.first, b = m.second;
+        hipLaunchKernelGGL(schur_cross_kernel, dim3(nblk(ax[b].r, 16), nblk(ax[a].r, 16)), dim3(256), 0,
+                           st, lam + ax[a].off, ax[a].r, (int)hoff[a], lam + ax[b].off, ax[b].r,
+                           (int)hoff[b], S, (int)nS);
+      }
+    for (int m = 0; m < L; ++m) {
+      if (is_hub[m]) continue;
+      std::vector<int> partners;   // all hubs: the leaves form an independent set
+      for (auto& md : mods) {
+        if (md.first == m) partners.push_back(md.second);
+        if (md.second == m) partners.push_back(md.first);
+      }
+      for (int K1 : partners)
+        for (int K2 : partners)
+          hipLaunchKernelGGL(schur_leaf_kernel, dim3(nblk(ax[K2].r, 16), nblk(ax[K1].r, 16)), dim3(256),
+                             0, st, lam + ax[K1].off, ax[K1].r, (int)hoff[K1], lam + ax[K2].off,
+                             ax[K2].r, (int)hoff[K2], lam + ax[m].off, ax[m].r, act + ax[m].off,
+                             h + ax[m].off, g + ax[m].off, damp, S, (int)nS, rhs, K1 == K2 ? 1 : 0);
+    }
+    hipLaunchKernelGGL(schur_pin_kernel, dim3(nblk(nS), (unsigned)nS), dim3(256), 0, st, act_hub,
+                       (int)nS, S, rhs);
+    GMGM_HIP(c, hipMemsetAsync(flag, 0, sizeof(int), st));
+    hipLaunchKernelGGL(cholesky_solve_kernel, dim3(1), dim3(1024), 0, st, S, (int)nS, rhs, flag);
+    for (int l : hub)
+      hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, rhs + hoff[l],
+                         g + ax[l].off, h + ax[l].off, act + ax[l].off, ax[l].r, d + ax[l].off);
+    for (int m = 0; m < L; ++m) {
+      if (is_hub[m]) continue;
+      GMGM_HIP(c, hipMemsetAsync(acc + ax[m].off, 0, ax[m].r * sizeof(double), st));
+      for (auto& md : mods) {
+        const int K = md.first == m ? md.second : md.second == m ? md.first : -1;
+        if (K < 0) continue;
+        hipLaunchKernelGGL(leaf_partner_kernel, dim3(nblk(ax[m].r, 4)), dim3(256), 0, st, lam + ax[m].off,
+                           ax[m].r, lam + ax[K].off, ax[K].r, act + ax[K].off, d + ax[K].off,
+                           acc + ax[m].off);
+      }
+      hipLaunchKernelGGL(leaf_step_kernel, dim3(nblk(ax[m].r)), dim3(256), 0, st, g + ax[m].off,
+                         h + ax[m].off, act + ax[m].off, acc + ax[m].off, ax[m].r, damp, d + ax[m].off);
+    }
+    int bad = 0;
+    GMGM_HIP(c, hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    GMGM_HIP(c, hipStreamSynchronize(st));
+    if (bad) return set_err(c, GMGM_E_NOCONV, "Newton system is not positive definite");
+    return GMGM_OK;
+  }
+};
+
+}  // namespace gmgm_sv
+
+using namespace gmgm_sv;
+
+extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64_t* ranks,
+                                       const double* const* E, int32_t n_mod,
+                                       const int32_t* modalities, const double* eps,
+                                       const double* const* warm, double tol, int32_t max_iter,
+                                       double* const* lambda_out, gmgm_solve_info* info) {
+  GMGM_CHECK_CTX(c);
+  if (n_axes < 2 || n_axes > MAX_AXES) return set_err(c, GMGM_E_ARG, "n_axes must be in [2, 8]");
+  if (n_mod < 1 || n_mod > n_axes * (n_axes - 1) / 2)
+    return set_err(c, GMGM_E_ARG, "n_mod must be in [1, n_axes (n_axes - 1) / 2]");
+  if (!ranks || !E || !modalities || !lambda_out) return set_err(c, GMGM_E_ARG, "null pointer argument");
+  if (!(tol > 0) || max_iter < 0) return set_err(c, GMGM_E_ARG, "need tol > 0 and max_iter >= 0");
+  Solver sv;
+  sv.c = c;
+  sv.st = c->stream;
+  sv.L = n_axes;
+  sv.ax.resize(n_axes);
+  for (int l = 0; l < n_axes; ++l) {
+    if (ranks[l] < 1 || ranks[l] > (1 << 26))
+      return set_err(c, GMGM_E_SHAPE, "axis %d: rank %lld outside [1, 2^26]", l, (long long)ranks[l]);
+    if (!E[l] || !lambda_out[l] || (warm && !warm[l]))
+      return set_err(c, GMGM_E_ARG, "axis %d: null pointer", l);
+    if (eps && !(eps[l] > 0 && std::isfinite(eps[l])))
+      return set_err(c, GMGM_E_DOMAIN, "axis %d: eps must be positive and finite", l);
+    sv.ax[l].r = (int)ranks[l];
+    sv.ax[l].off = sv.T;
+    sv.T += sv.ax[l].r;
+  }
+  if (sv.T > (size_t)1 << 28) return set_err(c, GMGM_E_SHAPE, "total rank too large");
+  std::vector<int> used(n_axes, 0);
+  for (int t = 0; t < n_mod; ++t) {
+    const int a = modalities[2 * t], b = modalities[2 * t + 1];
+    if (a < 0 || b < 0 || a >= n_axes || b >= n_axes || a == b)
+      return set_err(c, GMGM_E_ARG, "modality %d joins invalid axes (%d, %d)", t, a, b);
+    for (auto& m : sv.mods)
+      if ((m.first == a && m.second == b) || (m.first == b && m.second == a))
+        return set_err(c, GMGM_E_ARG, "modality %d repeats the axis pair (%d, %d)", t, a, b);
+    sv.mods.push_back({a, b});
+    used[a] = used[b] = 1;
+  }
+  for (int l = 0; l < n_axes; ++l)
+    if (!used[l]) return set_err(c, GMGM_E_ARG, "axis %d belongs to no modality", l);
+  sv.hub = hub_axes(sv.ax, sv.mods);
+  sv.is_hub.assign(n_axes, 0);
+  sv.hoff.assign(n_axes, 0);
+  for (int l : sv.hub) {
+    sv.is_hub[l] = 1;
+    sv.hoff[l] = sv.nS;
+    sv.nS += sv.ax[l].r;
+  }
+  if (sv.nS > (size_t)MAX_HUB)
+    return set_err(c, GMGM_E_SHAPE, "the Schur system has %zu unknowns (at most %d)", sv.nS, MAX_HUB);
+  GMGM_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = sv.st;
+  const size_t T = sv.T, nS = sv.nS;
+
+  void *w0, *w1;
+  GMGM_TRY(ws_get(c, WS_SOLVE0, T * sizeof(double) * 11 + 64 * sizeof(double), &w0));
+  GMGM_TRY(ws_get(c, WS_SOLVE1, nS * nS * 8 + nS * 8 + (T + nS + 64) * 4, &w1));
+  double* base = (double*)w0;
+  sv.lam = base;
+  sv.trial = base + T;
+  sv.Ec = base + 2 * T;
+  sv.s1 = base + 3 * T;
+  sv.s2 = base + 4 * T;
+  sv.lg = base + 5 * T;
+  sv.g = base + 6 * T;
+  sv.h = base + 7 * T;
+  sv.d = base + 8 * T;
+  sv.acc = base + 9 * T;
+  sv.kkt = base + 10 * T;
+  sv.scal = base + 11 * T;
+  sv.S = (double*)w1;
+  sv.rhs = sv.S + nS * nS;
+  sv.act = (int*)(sv.rhs + nS);
+  sv.act_hub = sv.act + T;
+  sv.flag = sv.act_hub + nS;
+
+  // E, the start point, domain checks, traces and largest E of each axis
+  GMGM_HIP(c, hipMemsetAsync(sv.flag, 0, sizeof(int), st));
+  for (int l = 0; l < n_axes; ++l) {
+    const Axis& a = sv.ax[l];
+    GMGM_HIP(c, hipMemcpyAsync(sv.Ec + a.off, E[l], a.r * sizeof(double), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(init_kernel, dim3(nblk(a.r)), dim3(256), 0, st, sv.Ec + a.off,
+                       warm ? warm[l] : (const double*)nullptr, a.r, sv.lam + a.off, sv.flag);
+    hipLaunchKernelGGL(init_kernel, dim3(nblk(a.r)), dim3(256), 0, st, sv.Ec + a.off,
+                       (const double*)nullptr, a.r, sv.trial + a.off, sv.flag);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.Ec + a.off,
+                       (const double*)nullptr, a.r, sv.scal + 2 * l);
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.Ec + a.off, a.r,
+                       sv.scal + 2 * l + 1);
+  }
+  int bad = 0;
+  GMGM_HIP(c, hipMemcpyAsync(&bad, sv.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  double tr[2 * MAX_AXES];
+  GMGM_TRY(sv.fetch(tr, sv.scal, 2 * n_axes));
+  if (bad == 1) return set_err(c, GMGM_E_DOMAIN, "every E must be positive and finite");
+  if (bad == 2) return set_err(c, GMGM_E_DOMAIN, "the warm start must be finite");
+  for (int l = 0; l < n_axes; ++l) {
+    sv.ax[l].trace = tr[2 * l];
+    sv.ax[l].eps = eps ? eps[l] : 1e-10 / tr[2 * l + 1];
+    hipLaunchKernelGGL(clip_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.trial + sv.ax[l].off,
+                       sv.ax[l].eps, sv.ax[l].r);
+  }
+  // the gauge of Algorithm 1's start max(1/E, eps) along each flat direction
+  const auto flats = flat_directions(sv.ax, sv.mods);
+  std::vector<double> target(flats.size(), 0.0);
+  for (size_t q = 0; q < flats.size(); ++q) GMGM_TRY(sv.gauge_value(sv.trial, flats[q], &target[q]));
+  auto fix_gauge = [&](double* v) -> gmgm_status {
+    for (size_t q = 0; q < flats.size(); ++q) {
+      double cur;
+      GMGM_TRY(sv.gauge_value(v, flats[q], &cur));
+      sv.shift(v, flats[q], target[q] - cur);
+    }
+    return GMGM_OK;
+  };
+  if (warm) GMGM_TRY(fix_gauge(sv.lam));
+  for (int l = 0; l < n_axes; ++l)
+    hipLaunchKernelGGL(clip_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.lam + sv.ax[l].off,
+                       sv.ax[l].eps, sv.ax[l].r);
+
+  double kres = 0;
+  GMGM_TRY(sv.gradient(sv.lam, &kres));
+  int it = 0;
+  bool stalled = false;
+  while (kres > tol && it < max_iter) {
+    it++;
+    double f0;
+    GMGM_TRY(sv.nll(sv.lam, &f0));
+    GMGM_TRY(sv.direction(std::min(1e-2, kres)));
+    for (auto& cdir : flats) {          // never move along a flat direction
+      double gv;
+      GMGM_TRY(sv.gauge_value(sv.d, cdir, &gv));
+      sv.shift(sv.d, cdir, -gv);
+    }
+    double alpha = 1.0;
+    bool accepted = false;
+    for (int ls = 0; ls < 60; ++ls) {
+      for (int l = 0; l < n_axes; ++l)
+        hipLaunchKernelGGL(trial_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.lam + sv.ax[l].off,
+                           sv.d + sv.ax[l].off, sv.ax[l].r, alpha, sv.ax[l].eps, sv.trial + sv.ax[l].off);
+      hipLaunchKernelGGL(pred_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.g, sv.d, sv.lam, sv.trial,
+                         sv.act, (int)T, alpha, sv.scal + 2);
+      double pred, f1;
+      GMGM_TRY(sv.fetch(&pred, sv.scal + 2, 1));
+      GMGM_TRY(sv.nll(sv.trial, &f1));
+      if (f1 <= f0 + 1e-4 * pred || std::fabs(pred) <= 1e-13 * (std::fabs(f0) + 1.0)) {
+        accepted = true;
+        break;
+      }
+      alpha *= 0.5;
+    }
+    if (!accepted) {
+      stalled = true;
+      break;
+    }
+    std::swap(sv.lam, sv.trial);
+    GMGM_TRY(sv.gradient(sv.lam, &kres));
+  }
+  GMGM_TRY(fix_gauge(sv.lam));
+  GMGM_TRY(sv.gradient(sv.lam, &kres));
+  for (int l = 0; l < n_axes; ++l)
+    GMGM_HIP(c, hipMemcpyAsync(lambda_out[l], sv.lam + sv.ax[l].off, sv.ax[l].r * sizeof(double),
+                               hipMemcpyDeviceToDevice, st));
+  if (info) {
+    for (int l = 0; l < n_axes; ++l)
+      hipLaunchKernelGGL(count_pinned_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.lam + sv.ax[l].off,
+                         sv.ax[l].eps, sv.ax[l].r, sv.scal + 4 + l);
+    double np[MAX_AXES];
+    GMGM_TRY(sv.fetch(np, sv.scal + 4, n_axes));
+    *info = gmgm_solve_info{};
+    info->iterations = it;
+    info->converged = kres <= tol;
+    info->n_flat = (int32_t)flats.size();
+    info->kkt = kres;
+    for (int l = 0; l < n_axes; ++l) {
+      info->n_pinned[l] = (int64_t)np[l];
+      info->eps[l] = sv.ax[l].eps;
+    }
+  }
+  GMGM_HIP(c, hipStreamSynchronize(st));
+  if (kres > tol)
+    return set_err(c, GMGM_E_NOCONV, "KKT residual %.3g after %d iterations%s", kres, it,
+                   stalled ? " (line search stalled)" : "");
+  return GMGM_OK;
+}

@@ -1,0 +1,183 @@
+"""Parity of gmgm_solve_eigs (HIP, through the C ABI) with the CPU oracle's
+projected-Newton solve of the eigenvalue MLE.
+
+Bar: the set of eigenvalues pinned at eps is identical; every other
+eigenvalue agrees within 1e-10 relative (plus 1e-12 of the axis maximum);
+the GPU's own KKT residual is <= the requested tolerance.  Spectra come from
+the seeded generators (generator Grams, Marchenko-Pastur + spikes at the
+workloads' shapes) and from the closed-form cases of the golden file.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import solver as S
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gpu_solve(lib, E, mods, eps=None, warm=None, tol=1e-12, max_iter=200, **kw):
+    import torch
+    Ed = [torch.from_numpy(np.ascontiguousarray(e, dtype=np.float64)).cuda() for e in E]
+    Wd = None if warm is None else [torch.from_numpy(np.ascontiguousarray(w, dtype=np.float64)).cuda()
+                                    for w in warm]
+    r = lib.solve_eigs(Ed, mods, eps=eps, warm=Wd, tol=tol, max_iter=max_iter, **kw)
+    return [x.cpu().numpy() for x in r.lam], r.info
+
+
+def _compare(prob, ref, lam, info, label):
+    assert info["converged"] and info["kkt"] <= 1e-12, (label, info)
+    for l in range(prob.n_axes):
+        pin_ref = ref.lam[l] <= prob.eps[l] * (1 + 1e-12)
+        pin_gpu = lam[l] <= prob.eps[l] * (1 + 1e-12)
+        assert np.array_equal(pin_ref, pin_gpu), (label, l, np.flatnonzero(pin_ref ^ pin_gpu)[:8])
+        assert info["n_pinned"][l] == int(pin_ref.sum()), (label, l)
+        assert abs(info["eps"][l] - prob.eps[l]) <= 1e-15 * prob.eps[l]
+        a, b = lam[l][~pin_gpu], ref.lam[l][~pin_ref]
+        err = np.abs(a - b) - (1e-10 * np.abs(b) + 1e-12 * np.max(ref.lam[l]))
+        assert np.all(err <= 0), (label, l, float(np.max(np.abs(a - b) / np.abs(b))))
+
+
+def _check_against_oracle(lib, E, mods, label, eps=None):
+    prob = S.Problem(E, mods, eps=eps)
+    ref = S.solve_eigs(prob)
+    assert ref.converged
+    lam, info = _gpu_solve(lib, E, mods, eps=eps)
+    _compare(prob, ref, lam, info, label)
+    return prob, ref, lam, info
+
+
+def test_closed_forms(lib):
+    with open(os.path.join(GOLDEN, "solver_closed_forms.json")) as f:
+        gold = json.load(f)
+    for case in gold["single_pair"]:
+        lam, info = _gpu_solve(lib, [np.array([case["E"]]), np.array([case["E"]])], [(0, 1)])
+        assert abs(lam[0][0] - case["psi"]) <= 1e-14 * case["psi"]
+        assert abs(lam[1][0] - case["phi"]) <= 1e-14 * case["phi"]
+        assert info["n_flat"] == 1
+    for case in gold["box"]:
+        Ec, Eg = np.array([case["Ec"]]), np.array(case["Eg"])
+        lam, info = _gpu_solve(lib, [Ec, Eg], [(0, 1)])
+        eps_g = 1e-10 / max(case["Eg"])
+        psi = 1.0 / (case["Ec"] - case["Eg"][1]) - eps_g
+        assert info["n_pinned"] == [0, 1] and info["n_flat"] == 0
+        assert abs(lam[0][0] - psi) <= 1e-12 * psi
+        assert lam[1][0] == eps_g
+        assert abs(lam[1][1] - (1.0 / case["Eg"][1] - psi)) <= 1e-12
+
+
+def test_balanced_equal_spectra(lib):
+    e = np.sort(np.random.default_rng(9).random(40) * 50 + 0.5)[::-1]
+    prob, ref, lam, info = _check_against_oracle(lib, [e, e.copy()], [(0, 1)], "balanced")
+    np.testing.assert_allclose(lam[0], lam[1], rtol=1e-13)
+    assert info["n_flat"] == 1
+
+
+@pytest.mark.parametrize("rc", [10, 30, 60])
+def test_generator_gram_spectra_partial_pinning(lib, rc):
+    X, _, _ = synth.nb_log1p(800, 60, 8, zipf=False, seed=11)
+    e, _ = oracle.eigh_desc(oracle.gram_dense(X))
+    prob, ref, lam, info = _check_against_oracle(lib, [e[:rc].copy(), e.copy()], [(0, 1)], f"rc={rc}")
+    if rc < 60:
+        assert 0 < info["n_pinned"][1] < 60
+
+
+@pytest.mark.parametrize("p,n,spikes,rc,rg", [(500, 2000, 8, 500, 500), (2000, 100_000, 20, 50, 2000),
+                                              (20_000, 1_000_000, 40, 100, 20_000)])
+def test_workload_shaped_spectra(lib, p, n, spikes, rc, rg):
+    """The three workloads' ranks (2000 x 500 cells x genes at full rank, 100k x 2000
+    with r_c = 50, 1M x 20k with r_c = 100) on Marchenko-Pastur + spike spectra."""
+    e = synth.spectrum_proxy(p, n, spikes, seed=7)
+    _check_against_oracle(lib, [e[:rc].copy(), e[:rg].copy()], [(0, 1)], f"{rc}x{rg}")
+
+
+def test_explicit_eps_and_unsorted_input(lib):
+    rng = np.random.default_rng(21)
+    Ec = rng.random(17) * 30 + 1
+    Eg = rng.random(23) * 10 + 0.5
+    _check_against_oracle(lib, [Ec, Eg], [(0, 1)], "eps", eps=[1e-6, 3e-7])
+
+
+def test_three_axes_shared_cells(lib):
+    """Two modalities sharing the cell axis (RNA genes and ATAC peaks)."""
+    rng = np.random.default_rng(15)
+    e = synth.spectrum_proxy(2000, 50_000, 12, seed=8)
+    Ec = e[:50].copy()
+    Eg = e.copy()
+    Ep = np.sort(rng.random(100) * e[60] + 0.1 * e[60])[::-1]
+    _check_against_oracle(lib, [Ec, Eg, Ep], [(0, 1), (0, 2)], "cells-genes-peaks")
+    Ec2 = np.sort(rng.random(8) * 40 + 5)[::-1]
+    Eg2 = np.sort(rng.random(12) * 20 + 1)[::-1]
+    Ep2 = np.sort(rng.random(6) * 20 + 1)[::-1]
+    _check_against_oracle(lib, [Ec2, Eg2, Ep2], [(0, 1), (0, 2)], "small 3-axis")
+
+
+def test_leaf_with_two_hubs_and_hub_pairs(lib):
+    """A triangle of modalities (the cover holds two hubs that share a leaf and
+    are joined to each other) and a 4-axis chain."""
+    rng = np.random.default_rng(16)
+    E = [np.sort(rng.random(r) * 20 + 1)[::-1] for r in (9, 7, 30)]
+    _check_against_oracle(lib, E, [(0, 1), (1, 2), (0, 2)], "triangle")
+    E4 = [np.sort(rng.random(r) * 10 + 1)[::-1] for r in (6, 40, 5, 33)]
+    _check_against_oracle(lib, E4, [(0, 1), (1, 2), (2, 3)], "chain")
+
+
+def test_warm_start(lib):
+    e = synth.spectrum_proxy(2000, 100_000, 20, seed=9)
+    X, _, _ = synth.nb_log1p(800, 60, 8, zipf=False, seed=11)
+    e2, _ = oracle.eigh_desc(oracle.gram_dense(X))
+    rng = np.random.default_rng(3)
+    for E in ([e[:50].copy(), e[:2000].copy()], [e2[:30].copy(), e2.copy()], [e2.copy(), e2.copy()]):
+        prob = S.Problem(E, [(0, 1)])
+        ref = S.solve_eigs(prob)
+        cold, cinfo = _gpu_solve(lib, E, [(0, 1)])
+        warm = [x * np.exp(0.01 * rng.standard_normal(x.size)) for x in ref.lam]
+        lam, info = _gpu_solve(lib, E, [(0, 1)], warm=warm)
+        _compare(prob, ref, lam, info, "warm")
+        assert info["iterations"] <= cinfo["iterations"]
+
+
+def test_deterministic(lib):
+    X, _, _ = synth.nb_log1p(800, 60, 8, zipf=False, seed=11)
+    e, _ = oracle.eigh_desc(oracle.gram_dense(X))
+    a, _ = _gpu_solve(lib, [e[:30].copy(), e.copy()], [(0, 1)])
+    b, _ = _gpu_solve(lib, [e[:30].copy(), e.copy()], [(0, 1)])
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_errors(lib):
+    import torch
+    E = [np.array([3.0, 2.0]), np.array([1.0, 0.5, 0.25])]
+    for bad_E, status in (([np.array([3.0, -1.0]), E[1]], 3), ([np.array([3.0, np.nan]), E[1]], 3)):
+        with pytest.raises(lib.GmgmError) as ei:
+            _gpu_solve(lib, bad_E, [(0, 1)])
+        assert ei.value.status == status
+    for mods in ([(0, 0)], [(0, 2)], [(0, 1), (1, 0)]):
+        with pytest.raises(lib.GmgmError) as ei:
+            _gpu_solve(lib, E, mods)
+        assert ei.value.status == 1
+    with pytest.raises(lib.GmgmError) as ei:        # an axis in no modality
+        _gpu_solve(lib, E + [np.array([1.0])], [(0, 1)])
+    assert ei.value.status == 1
+    with pytest.raises(lib.GmgmError) as ei:
+        _gpu_solve(lib, E, [(0, 1)], eps=[1e-9, -1.0])
+    assert ei.value.status == 3
+    with pytest.raises(lib.GmgmError) as ei:        # iteration limit
+        _gpu_solve(lib, E, [(0, 1)], max_iter=1)
+    assert ei.value.status == 4
+    lam, info = _gpu_solve(lib, E, [(0, 1)], max_iter=1, raise_on_noconv=False)
+    assert not info["converged"] and info["iterations"] == 1
+    with pytest.raises(lib.GmgmError) as ei:        # Schur system too large
+        big = np.linspace(2.0, 1.0, 2100)
+        _gpu_solve(lib, [big, big.copy()], [(0, 1)])
+    assert ei.value.status == 2
+    # the context stays usable
+    lam, info = _gpu_solve(lib, E, [(0, 1)])
+    assert info["converged"]
