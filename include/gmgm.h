@@ -127,6 +127,60 @@ gmgm_status gmgm_recompose_topk(gmgm_ctx_t ctx, int64_t n, int64_t r, const floa
                                 int64_t* row_ptr_out, int32_t* col_out, float* val_out,
                                 gmgm_topk_stats* stats);
 
+/*
+ * Small-axis Gram matrix G = X^T X (problem setup: S_l = mat_l[D] mat_l[D]^T,
+ * formed only for the small axis; no centring or scaling).
+ *
+ *   n, p        X is n x p (cells x genes); 1 <= p <= 65536.
+ *   nnz         number of stored entries.
+ *   row_ptr     n + 1 int64 (device), row_ptr[0] = 0, non-decreasing, <= nnz.
+ *   col         nnz int32 column indices in [0, p) (device).  Duplicates add up.
+ *   val         nnz FP32 values (device), or NULL for all ones (binary data).
+ *   G           p x p FP32 output, row-major (device); exactly symmetric.
+ * FP32 products accumulate in FP32 over at most 2048 rows, then in FP64.
+ * Workspace: a dense panel of X rows (<= 2 GiB) and FP64 partial sums
+ * (p_pad^2 x splits, <= 8 GiB, p_pad = p rounded up to 256).  Malformed CSR is
+ * reported as GMGM_E_SHAPE and non-finite values as GMGM_E_DOMAIN by the next
+ * synchronising call; asynchronous otherwise.
+ */
+gmgm_status gmgm_gram(gmgm_ctx_t ctx, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                      const int32_t* col, const float* val, float* G);
+
+/*
+ * FP64 eigendecomposition of the symmetric Gram (Algorithm 1, first loop;
+ * Theorem 1 makes these eigenvectors the MLE's).
+ *
+ *   p           1 <= p <= 46340.
+ *   G           p x p FP32 symmetric (device, row-major); its upper triangle
+ *               (row <= column) is read.
+ *   evals       p FP64 (device), descending.
+ *   evecs       p x p FP64 (device), column-major: column j (evecs[j p .. j p + p))
+ *               is the unit eigenvector of evals[j].
+ *   rank_out    host, or NULL: numerical rank #{j : evals[j] > p 2^-52 evals[0]}.
+ * Uses rocSOLVER's divide-and-conquer solver on an FP64 copy.  Synchronises.
+ * GMGM_E_DOMAIN for non-finite G, GMGM_E_NOCONV if the solver reports failure.
+ */
+gmgm_status gmgm_eigh_small(gmgm_ctx_t ctx, int64_t p, const float* G, double* evals, double* evecs,
+                            int64_t* rank_out);
+
+/*
+ * Cell-axis factor ("top r left singular vectors" of X, Algorithm 1 first
+ * loop) through the exact identity U = X V[:, :r] diag(e[:r])^(-1/2).
+ *
+ *   n, p, nnz, row_ptr, col, val   X in CSR as for gmgm_gram.
+ *   evecs       column-major FP64 eigenvectors (device), column j at
+ *               evecs + j ldv; ldv >= p.
+ *   evals       >= r positive FP64 eigenvalues (device).
+ *   r           1 <= r <= min(p, 256).
+ *   U           n x r FP32 output, row-major (device).
+ * FP64 accumulation of FP32 X times the FP32-rounded scaled eigenvectors.
+ * Asynchronous; malformed CSR -> GMGM_E_SHAPE, non-finite or non-positive
+ * eigenvalues / non-finite values -> GMGM_E_DOMAIN at the next synchronising call.
+ */
+gmgm_status gmgm_sketch(gmgm_ctx_t ctx, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                        const int32_t* col, const float* val, const double* evecs, int64_t ldv,
+                        const double* evals, int64_t r, float* U);
+
 /* Result of one gmgm_solve_eigs call. */
 typedef struct {
   int32_t iterations;       /* Newton iterations taken */

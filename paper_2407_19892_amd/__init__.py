@@ -57,6 +57,9 @@ SIGNATURES = {
     "gmgm_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "gmgm_recompose_topk": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, _I64, _I32, ctypes.c_int,
                                            _I32, _P, _P, _P, ctypes.POINTER(TopkStats)]),
+    "gmgm_gram": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
+    "gmgm_eigh_small": (ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.POINTER(_I64)]),
+    "gmgm_sketch": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _I64, _P, _I64, _P]),
     "gmgm_solve_eigs": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_P), _I32,
                                        ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(_P), ctypes.c_double, _I32, ctypes.POINTER(_P),
@@ -218,3 +221,63 @@ def solve_eigs(E, modalities, eps=None, warm=None, tol: float = 1e-12, max_iter:
         return SolveResult(out, d)
     _check(c, st)
     return SolveResult(out, d)
+
+
+def _csr_args(row_ptr, col, val, n):
+    import torch
+    if not (row_ptr.is_cuda and row_ptr.dtype == torch.int64 and row_ptr.numel() == n + 1):
+        raise TypeError("row_ptr must be an int64 device tensor of n + 1 entries")
+    if not (col.is_cuda and col.dtype == torch.int32):
+        raise TypeError("col must be an int32 device tensor")
+    if val is not None and not (val.is_cuda and val.dtype == torch.float32 and val.numel() == col.numel()):
+        raise TypeError("val must be a float32 device tensor like col (or None)")
+    for t in (row_ptr, col) + ((val,) if val is not None else ()):
+        if not t.is_contiguous():
+            raise ValueError("CSR tensors must be contiguous")
+    return _ptr(row_ptr), _ptr(col), (_ptr(val) if val is not None else None), col.numel()
+
+
+def gram(row_ptr, col, val, n: int, p: int, out=None, check: bool = True):
+    """G = X^T X (p x p, FP32) of the CSR matrix X (n x p); see gmgm_gram."""
+    import torch
+    rp, cp, vp, nnz = _csr_args(row_ptr, col, val, n)
+    G = torch.empty(p, p, dtype=torch.float32, device=row_ptr.device) if out is None else out
+    c = context(row_ptr.device.index)
+    _check(c, load().gmgm_gram(c, n, p, nnz, rp, cp, vp, _ptr(G)))
+    if check:
+        _check(c, load().gmgm_sync(c))
+    return G
+
+
+def eigh_small(G):
+    """(evals descending, evecs column-major as a (p, p) tensor whose ROW j is
+    eigenvector j, numerical rank) of the symmetric FP32 Gram; see gmgm_eigh_small."""
+    import torch
+    if not (G.is_cuda and G.dtype == torch.float32 and G.dim() == 2 and G.shape[0] == G.shape[1]
+            and G.is_contiguous()):
+        raise TypeError("G must be a contiguous square float32 device tensor")
+    p = G.shape[0]
+    w = torch.empty(p, dtype=torch.float64, device=G.device)
+    Vt = torch.empty(p, p, dtype=torch.float64, device=G.device)
+    rank = _I64()
+    c = context(G.device.index)
+    _check(c, load().gmgm_eigh_small(c, p, _ptr(G), _ptr(w), _ptr(Vt), ctypes.byref(rank)))
+    return w, Vt, rank.value
+
+
+def sketch(row_ptr, col, val, n: int, p: int, Vt, evals, r: int, out=None, check: bool = True):
+    """U = X V[:, :r] diag(e[:r])^-1/2 (n x r FP32).  Vt is the column-major
+    eigenvector storage returned by eigh_small (row j = eigenvector j)."""
+    import torch
+    rp, cp, vp, nnz = _csr_args(row_ptr, col, val, n)
+    if not (Vt.is_cuda and Vt.dtype == torch.float64 and Vt.is_contiguous() and Vt.dim() == 2
+            and Vt.shape[1] >= p and Vt.shape[0] >= r):
+        raise TypeError("Vt must be a contiguous float64 device tensor of shape (>= r, >= p)")
+    if not (evals.is_cuda and evals.dtype == torch.float64 and evals.numel() >= r):
+        raise TypeError("evals must be a float64 device tensor with >= r entries")
+    U = torch.empty(n, r, dtype=torch.float32, device=row_ptr.device) if out is None else out
+    c = context(row_ptr.device.index)
+    _check(c, load().gmgm_sketch(c, n, p, nnz, rp, cp, vp, _ptr(Vt), Vt.shape[1], _ptr(evals), r, _ptr(U)))
+    if check:
+        _check(c, load().gmgm_sync(c))
+    return U

@@ -1,4 +1,6 @@
 // Context, errors, workspace and synchronisation of the C ABI.
+#include <rocblas/rocblas.h>
+
 #include "gmgm_internal.h"
 
 gmgm_status set_err(gmgm_ctx* c, gmgm_status s, const char* fmt, ...) {
@@ -41,6 +43,19 @@ gmgm_status ws_get(gmgm_ctx* c, int slot, size_t bytes, void** out) {
     b.bytes = want;
   }
   *out = b.ptr;
+  return GMGM_OK;
+}
+
+gmgm_status blas_handle(gmgm_ctx* c, void** out) {
+  if (!c->rocblas) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success)
+      return set_err(c, GMGM_E_HIP, "rocblas_create_handle failed");
+    c->rocblas = h;
+  }
+  if (rocblas_set_stream((rocblas_handle)c->rocblas, c->stream) != rocblas_status_success)
+    return set_err(c, GMGM_E_HIP, "rocblas_set_stream failed");
+  *out = c->rocblas;
   return GMGM_OK;
 }
 
@@ -129,6 +144,7 @@ extern "C" void gmgm_destroy(gmgm_ctx_t c) {
     (void)hipEventDestroy(p.second);
   }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->rocblas) (void)rocblas_destroy_handle((rocblas_handle)c->rocblas);
   for (auto& b : c->bufs)
     if (b.ptr) (void)hipFree(b.ptr);
   (void)hipFree(c->dev_status);
@@ -157,6 +173,9 @@ extern "C" gmgm_status gmgm_sync(gmgm_ctx_t c) {
     GMGM_HIP(c, hipStreamSynchronize(c->stream));
     if (s == DEV_NONFINITE) return set_err(c, GMGM_E_DOMAIN, "a kernel found a non-finite input");
     if (s == DEV_OVERFLOW) return set_err(c, GMGM_E_OVERFLOW, "a device buffer overflowed");
+    if (s == DEV_BADINDEX)
+      return set_err(c, GMGM_E_SHAPE, "malformed CSR input (row_ptr not monotone within [0, nnz] or a "
+                                      "column index outside [0, p))");
     return set_err(c, GMGM_E_HIP, "device fault code %d", s);
   }
   return GMGM_OK;

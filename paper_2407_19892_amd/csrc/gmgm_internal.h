@@ -13,7 +13,7 @@
 #include "../../include/gmgm.h"
 
 // Device-side fault codes written into the context's status word.
-enum : int { DEV_OK = 0, DEV_NONFINITE = 1, DEV_OVERFLOW = 2 };
+enum : int { DEV_OK = 0, DEV_NONFINITE = 1, DEV_OVERFLOW = 2, DEV_BADINDEX = 3 };
 
 // A device buffer the context owns and grows on demand.
 struct DevBuf {
@@ -42,12 +42,15 @@ void timing_stop(gmgm_ctx* c, hipEvent_t start);
 // Workspace slots.
 enum WsSlot : int {
   WS_VP = 0, WS_WP, WS_NORMS, WS_CAND, WS_MISC, WS_FALLBACK, WS_SCALES, WS_VP2, WS_WP2, WS_CAND2,
-  WS_GRAM0, WS_GRAM1, WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_MLP0, WS_MLP1,
+  WS_GRAM0, WS_GRAM1, WS_GRAM2, WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_MLP0, WS_MLP1, WS_EIGH0,
+  WS_EIGH1, WS_SKETCH,
   WS_COUNT
 };
 
 gmgm_status set_err(gmgm_ctx* c, gmgm_status s, const char* fmt, ...);
 gmgm_status hip_err(gmgm_ctx* c, hipError_t e, const char* what);
+// The context's rocBLAS handle (created on first use, bound to the context stream).
+gmgm_status blas_handle(gmgm_ctx* c, void** out);
 // Pointer to a workspace slot of at least `bytes` bytes (grown when needed).
 gmgm_status ws_get(gmgm_ctx* c, int slot, size_t bytes, void** out);
 

@@ -1,0 +1,268 @@
+// Small-axis Gram matrix G = X^T X of a CSR cells x genes matrix (FP32 MFMA).
+//
+// The Gram of the gene axis (S_l = mat_l[D] mat_l[D]^T of the problem setup,
+// formed only for the small axis; the large axis is reached through its
+// singular vectors, Algorithm 1's first loop).  No centring or scaling.
+//
+// Design: row panels of X are densified into HBM (zero-padded to a multiple
+// of 256 genes), then a symmetric rank-k update runs on the FP32 MFMA
+// (32x32x2): one 256 x 256 output tile per workgroup of 16 waves (64 x 64
+// each), only tiles with J >= I,
+// 32-row chunks staged through LDS (double buffered).  Each workgroup folds
+// its FP32 accumulators into an FP64 partial sum every 2048 rows, so the
+// FP32 rounding error of a sum grows with at most 2048 terms; long K ranges
+// are split across workgroups (one FP64 partial per split).  A final kernel
+// adds the splits in fixed order, mirrors the upper triangle and rounds to
+// FP32.  Results are deterministic for CSR input without duplicate columns.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "gmgm_internal.h"
+#include "mfma_util.h"
+
+namespace gmgm_gr {
+
+constexpr int GT = 256;           // output tile edge
+constexpr int KC = 32;            // rows per LDS stage
+constexpr int LST = 288;          // LDS row stride (floats): rows k and k+1 fall in disjoint bank halves
+constexpr int FLUSH_CHUNKS = 64;  // FP32 -> FP64 fold period: 64 * 32 = 2048 rows
+constexpr int THREADS = 1024;    // 16 waves, each a 64 x 64 block of the tile
+
+struct TileArgs {
+  const float* D;      // panel: rows_pad x pp, row-major, zero padded
+  int64_t pp;          // padded gene count (multiple of GT)
+  int64_t rows_pad;    // panel rows (multiple of KC)
+  int64_t rows_split;  // rows per split (multiple of KC)
+  const int2* tiles;   // (I, J), J >= I
+  double* P;           // n_split x pp x pp FP64 partials
+};
+
+__global__ void __launch_bounds__(THREADS) gram_tile_kernel(TileArgs a) {
+  __shared__ float lds[2][2][KC][LST];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 2, wc = w & 3, half = lane >> 5, l32 = lane & 31;
+  const int2 IJ = a.tiles[blockIdx.x];
+  const int s = blockIdx.y;
+  const int64_t k_begin = (int64_t)s * a.rows_split;
+  const int64_t k_end = k_begin + a.rows_split < a.rows_pad ? k_begin + a.rows_split : a.rows_pad;
+  if (k_begin >= k_end) return;
+  const int nchunks = (int)((k_end - k_begin) / KC);
+  const float* Abase = a.D + (size_t)k_begin * a.pp + (size_t)IJ.x * GT;
+  const float* Bbase = a.D + (size_t)k_begin * a.pp + (size_t)IJ.y * GT;
+
+  // staging: thread t moves float4s q = t and q = t + 1024 of each 32 x 256 operand chunk
+  const int q0 = tid, q1 = tid + THREADS;
+  const size_t g0 = (size_t)(q0 >> 6) * a.pp + 4 * (q0 & 63), g1 = (size_t)(q1 >> 6) * a.pp + 4 * (q1 & 63);
+  float4 ra0, ra1, rb0, rb1;
+  auto load = [&](int c) {
+    const size_t off = (size_t)c * KC * a.pp;
+    ra0 = *reinterpret_cast<const float4*>(Abase + off + g0);
+    ra1 = *reinterpret_cast<const float4*>(Abase + off + g1);
+    rb0 = *reinterpret_cast<const float4*>(Bbase + off + g0);
+    rb1 = *reinterpret_cast<const float4*>(Bbase + off + g1);
+  };
+  auto store = [&](int buf) {
+    *reinterpret_cast<float4*>(&lds[buf][0][q0 >> 6][4 * (q0 & 63)]) = ra0;
+    *reinterpret_cast<float4*>(&lds[buf][0][q1 >> 6][4 * (q1 & 63)]) = ra1;
+    *reinterpret_cast<float4*>(&lds[buf][1][q0 >> 6][4 * (q0 & 63)]) = rb0;
+    *reinterpret_cast<float4*>(&lds[buf][1][q1 >> 6][4 * (q1 & 63)]) = rb1;
+  };
+
+  v16f acc[2][2];
+  auto zero_acc = [&]() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+  };
+  double* Pt = a.P + (size_t)s * a.pp * a.pp + (size_t)IJ.x * GT * a.pp + (size_t)IJ.y * GT;
+  auto fold = [&]() {
+    // an opaque copy of the row stride keeps the 64 destination addresses from
+    // being hoisted out of the K loop (they would not fit the register budget)
+    int ld = (int)a.pp;
+    asm volatile("" : "+s"(ld));
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wr * 64 + i * 32 + acc_row(v, half);
+          const int col = wc * 64 + j * 32 + l32;
+          double* dst = Pt + (size_t)row * ld + col;
+          *dst = *dst + (double)acc[i][j][v];
+          // keep at most four read-modify-writes in flight (register budget)
+          if (v % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+  };
+
+  zero_acc();
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunks) load(c + 1);
+#pragma unroll
+    for (int kk = 0; kk < KC / 2; ++kk) {
+      const int k = 2 * kk + half;
+      float av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = lds[buf][0][k][wr * 64 + i * 32 + l32];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = lds[buf][1][k][wc * 64 + j * 32 + l32];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+      // operands of at most two K steps ahead: 4 MFMAs (256 cycles) hide an LDS read
+      if (kk % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    if ((c + 1) % FLUSH_CHUNKS == 0 || c + 1 == nchunks) {
+      fold();
+      zero_acc();
+    }
+    if (c + 1 < nchunks) store(buf ^ 1);
+    __syncthreads();
+  }
+}
+
+// Zero-fill of n floats (n multiple of 4) / n doubles.
+__global__ void fill_f32_kernel(float4* __restrict__ p, int64_t n4) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+__global__ void fill_f64_kernel(double2* __restrict__ p, int64_t n2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_double2(0.0, 0.0);
+}
+
+// Scatter CSR rows [r0, r0 + rows) into the zeroed panel (one wave per row).
+// Malformed rows (row_ptr decreasing or beyond nnz, column outside [0, p)) are
+// skipped and reported; duplicate columns add up.
+__global__ void __launch_bounds__(256) densify_kernel(const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col,
+                                                      const float* __restrict__ val, int64_t nnz,
+                                                      int64_t p, int64_t r0, int64_t rows,
+                                                      int64_t pp, float* __restrict__ D,
+                                                      int* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= rows) return;
+  const int64_t b = rp[r0 + i], e = rp[r0 + i + 1];
+  if (b < 0 || e < b || e > nnz) {
+    if (lane == 0) atomicCAS(status, 0, DEV_BADINDEX);
+    return;
+  }
+  bool badc = false, badv = false;
+  float* row = D + (size_t)i * pp;
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int c = col[t];
+    const float v = val ? val[t] : 1.0f;
+    if (c < 0 || c >= p) {
+      badc = true;
+      continue;
+    }
+    badv |= !isfinite(v);
+    unsafeAtomicAdd(row + c, v);
+  }
+  if (__ballot(badc) && lane == 0) atomicCAS(status, 0, DEV_BADINDEX);
+  if (__ballot(badv) && lane == 0) atomicCAS(status, 0, DEV_NONFINITE);
+}
+
+// G (p x p, row-major FP32) from the FP64 split partials: sum the splits in
+// order, take the upper triangle's value for both (a, b) and (b, a).
+__global__ void __launch_bounds__(256) gram_finish_kernel(const double* __restrict__ P, int n_split,
+                                                          int64_t pp, int64_t p,
+                                                          float* __restrict__ G) {
+  __shared__ double t[32][33];
+  const int A = blockIdx.y, B = blockIdx.x;
+  const int lo = A < B ? A : B, hi = A < B ? B : A;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const size_t idx = (size_t)(lo * 32 + r) * pp + hi * 32 + tx;
+    double s = 0.0;
+    for (int q = 0; q < n_split; ++q) s += P[(size_t)q * pp * pp + idx];
+    t[r][tx] = s;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t a = (int64_t)A * 32 + r, b = (int64_t)B * 32 + tx;
+    if (a >= p || b >= p) continue;
+    double v;
+    if (A < B) v = t[r][tx];
+    else if (A > B) v = t[tx][r];
+    else v = r <= tx ? t[r][tx] : t[tx][r];
+    G[a * p + b] = (float)v;
+  }
+}
+
+inline unsigned grid_for(int64_t n, int per_block) {
+  const int64_t g = (n + per_block - 1) / per_block;
+  return (unsigned)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
+}
+
+}  // namespace gmgm_gr
+
+using namespace gmgm_gr;
+
+extern "C" gmgm_status gmgm_gram(gmgm_ctx_t c, int64_t n, int64_t p, int64_t nnz,
+                                 const int64_t* row_ptr, const int32_t* col, const float* val,
+                                 float* G) {
+  GMGM_CHECK_CTX(c);
+  if (n < 1 || p < 1 || p > 65536 || nnz < 0)
+    return set_err(c, GMGM_E_SHAPE, "need n >= 1, 1 <= p <= 65536, nnz >= 0 (got n=%lld p=%lld nnz=%lld)",
+                   (long long)n, (long long)p, (long long)nnz);
+  if (!row_ptr || !G || (nnz > 0 && !col)) return set_err(c, GMGM_E_ARG, "null pointer argument");
+  GMGM_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  const int64_t pp = (p + GT - 1) / GT * GT;
+  const int nt = (int)(pp / GT);
+  const int n_tiles = nt * (nt + 1) / 2;
+  // panel rows: about 2 GiB of densified rows per panel
+  int64_t nb = ((int64_t)1 << 31) / (pp * 4) / KC * KC;
+  nb = std::max<int64_t>(KC, std::min<int64_t>(nb, (n + KC - 1) / KC * KC));
+  // K splits: enough workgroups to cover the chip, each split >= 256 rows,
+  // partials at most 8 GiB
+  int n_split = (int)std::min<int64_t>(64, (1024 + n_tiles - 1) / n_tiles);
+  n_split = (int)std::max<int64_t>(1, std::min<int64_t>(n_split, nb / 256));
+  while (n_split > 1 && (double)n_split * pp * pp * 8 > 8.0 * (1 << 30)) n_split--;
+
+  void *wD, *wP, *wT;
+  GMGM_TRY(ws_get(c, WS_GRAM0, (size_t)nb * pp * sizeof(float), &wD));
+  GMGM_TRY(ws_get(c, WS_GRAM1, (size_t)n_split * pp * pp * sizeof(double), &wP));
+  GMGM_TRY(ws_get(c, WS_GRAM2, (size_t)n_tiles * sizeof(int2), &wT));
+  std::vector<int2> tiles;
+  tiles.reserve(n_tiles);
+  for (int I = 0; I < nt; ++I)
+    for (int J = I; J < nt; ++J) tiles.push_back(make_int2(I, J));
+  GMGM_HIP(c, hipMemcpyAsync(wT, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  // the host vector must outlive the copy
+  GMGM_HIP(c, hipStreamSynchronize(st));
+  float* D = (float*)wD;
+  double* P = (double*)wP;
+  const int64_t np2 = (int64_t)n_split * pp * pp / 2;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(np2, 256)), dim3(256), 0, st, (double2*)P, np2);
+  for (int64_t r0 = 0; r0 < n; r0 += nb) {
+    const int64_t rows = std::min<int64_t>(nb, n - r0);
+    const int64_t rows_pad = (rows + KC - 1) / KC * KC;
+    const int64_t n4 = rows_pad * pp / 4;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n4, 256)), dim3(256), 0, st, (float4*)D, n4);
+    hipLaunchKernelGGL(densify_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, row_ptr, col, val,
+                       nnz, p, r0, rows, pp, D, c->dev_status);
+    const int64_t rs = ((rows_pad + n_split - 1) / n_split + KC - 1) / KC * KC;
+    TileArgs ta{D, pp, rows_pad, rs, (const int2*)wT, P};
+    hipEvent_t ev = timing_start(c);
+    hipLaunchKernelGGL(gram_tile_kernel, dim3((unsigned)n_tiles, (unsigned)n_split), dim3(THREADS), 0, st, ta);
+    timing_stop(c, ev);
+  }
+  const unsigned g32 = (unsigned)((p + 31) / 32);
+  hipLaunchKernelGGL(gram_finish_kernel, dim3(g32, g32), dim3(256), 0, st, P, n_split, pp, p, G);
+  GMGM_HIP(c, hipGetLastError());
+  return GMGM_OK;
+}

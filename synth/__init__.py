@@ -37,6 +37,7 @@ __all__ = [
     "nb_log1p_rows",
     "dense_to_csr",
     "cell_factor_proxy",
+    "csr_proxy",
     "spectrum_proxy",
     "config",
     "ROW_BLOCK",
@@ -221,3 +222,43 @@ def spectrum_proxy(p: int, n: int, n_spikes: int, seed: int, scale: float = 1.0)
     e = np.concatenate([spikes, bulk])
     e = np.sort(e)[::-1][:m] * scale
     return np.ascontiguousarray(e)
+
+
+def _csr_proxy_block(b: int, n: int, p: int, density: float, seed: int, block: int):
+    rows = min(block, n - b * block)
+    rng = np.random.Generator(np.random.Philox(key=[seed, 0xC5B0000 + b]))
+    s = rng.lognormal(0.0, 0.25, rows)
+    s /= math.exp(0.25 ** 2 / 2)
+    d = np.clip(density * s, 1e-6, 0.999)
+    m_max = int(p * float(d.max()) * 1.5 + 100)
+    gaps = rng.geometric(d[:, None], size=(rows, m_max))
+    pos = np.cumsum(gaps, axis=1, dtype=np.int64) - 1
+    mask = pos < p
+    assert not mask[:, -1].any(), "position budget exhausted"
+    c = rng.geometric(0.6, size=int(mask.sum()))
+    return mask.sum(axis=1), pos[mask].astype(np.int32), np.log1p(c).astype(np.float32)
+
+
+def csr_proxy(n: int, p: int, density: float, seed: int, block: int = 16384, workers: int = 1):
+    """Fast CSR stand-in for ``nb_log1p`` at large sizes (same shape and density,
+    log1p-of-small-count values, per-cell depth variation), without the cluster
+    and factor structure.  Returns (row_ptr int64, col int32 ascending per row,
+    val float32).  Row block b draws from Philox key (seed, 0xC5B0000 + b), so
+    the result does not depend on ``workers`` (processes generating blocks).
+
+    Per row i: depth s_i ~ lognormal(0, 0.25) scaled to mean 1, nonzero
+    positions from geometric gaps with success probability density * s_i
+    (a Bernoulli(density * s_i) pattern), counts ~ Geometric(0.6) >= 1 and
+    values log1p(count)."""
+    nblk = (n + block - 1) // block
+    args = [(b, n, p, density, seed, block) for b in range(nblk)]
+    if workers > 1 and nblk > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            parts = list(ex.map(_csr_proxy_block, *zip(*args)))
+    else:
+        parts = [_csr_proxy_block(*a) for a in args]
+    counts = np.concatenate([q[0] for q in parts])
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return row_ptr, np.concatenate([q[1] for q in parts]), np.concatenate([q[2] for q in parts])
