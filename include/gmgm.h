@@ -186,7 +186,7 @@ typedef struct {
   int32_t iterations;       /* Newton iterations taken */
   int32_t converged;        /* 1 if the KKT residual reached tol */
   int32_t n_flat;           /* number of zero-slope shift directions fixed by the gauge rule */
-  int32_t reserved;
+  int32_t warm_used;        /* 1 if the warm start was used (its NLL was not above 1/E's) */
   double kkt;               /* final scaled KKT residual */
   int64_t n_pinned[8];      /* per axis: eigenvalues that end at their bound eps_l */
   double eps[8];            /* per axis: the bound used */
@@ -202,7 +202,10 @@ typedef struct {
  * modality graph, Cholesky of that system on the device), Armijo search, FP64
  * throughout, deterministic reductions.  Start: Algorithm 1's 1/E, or `warm`.
  * Shift directions along which the NLL is flat (every modality's two axes
- * shifted by +c and -c with equal traces) are fixed to the gauge of 1/E.
+ * shifted by +c and -c with equal traces) are fixed to the gauge of 1/E.  A
+ * warm start is moved to that gauge, clipped to the box, and used only when
+ * its NLL is not above that of 1/E.  Per iteration a free eigenvalue may
+ * shrink by at most a factor 64.
  *
  *   n_axes       2..8 axes.
  *   ranks        host, n_axes retained ranks r_l >= 1.
@@ -229,6 +232,61 @@ gmgm_status gmgm_solve_eigs(gmgm_ctx_t ctx, int32_t n_axes, const int64_t* ranks
                             const double* const* E, int32_t n_mod, const int32_t* modalities,
                             const double* eps, const double* const* warm, double tol,
                             int32_t max_iter, double* const* lambda_out, gmgm_solve_info* info);
+
+/*
+ * Learned warm start of the eigenvalue MLE: a small network predicts the
+ * solution from the two axes' spectra and replaces Algorithm 1's start
+ * lambda^0 = 1/E (gmgm_solve_eigs then finishes from it; its result does not
+ * depend on the start).  The paper fixes no network; this one is:
+ *   features (1028 FP32): each axis' log-spectrum resampled to 512 bins at the
+ *     0-based fractional indices t_b = (b + 1/2) r / 512 - 1/2 (clamped to
+ *     [0, r-1], linear interpolation), both shifted by max(log E_c[0], log E_g[0]),
+ *     then log r_c, log r_g, log d_c, log d_g;
+ *   network: 1028 -> 256 -> 256 -> 1024, SiLU after the hidden layers;
+ *     parameters are one FP32 vector W1 (256x1028), b1, W2 (256x256), b2,
+ *     W3 (1024x256), b3, row-major, gmgm_ws_param_count() floats;
+ *   outputs (1024 FP32): two 512-bin curves of log(lambda E) (cell axis, then
+ *     gene axis);
+ *   loss: masked mean squared error against targets resampled the same way;
+ *   optimiser: AdamW (0.9, 0.999, eps 1e-8, decoupled weight decay).
+ * All arrays are device pointers; spectra are FP64 and descending.
+ */
+int64_t gmgm_ws_param_count(void);
+
+/* Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) initialisation from a SplitMix64
+ * hash of (seed, index).  Asynchronous. */
+gmgm_status gmgm_ws_init(gmgm_ctx_t ctx, float* params, uint64_t seed);
+
+/* The 1028 features of an axis pair (E_c: r_c values, E_g: r_g values, both
+ * positive; d_c, d_g the axes' dimensions >= 1).  Asynchronous; non-positive
+ * E is reported as GMGM_E_DOMAIN by the next synchronising call. */
+gmgm_status gmgm_ws_features(gmgm_ctx_t ctx, const double* Ec, int64_t rc, const double* Eg, int64_t rg,
+                             double dc, double dg, float* feat);
+
+/* Training targets (1024): resampled log(lambda_c E_c) and log(lambda_g E_g)
+ * of a solved problem.  Asynchronous. */
+gmgm_status gmgm_ws_targets(gmgm_ctx_t ctx, const double* Ec, const double* lam_c, int64_t rc,
+                            const double* Eg, const double* lam_g, int64_t rg, float* target);
+
+/* out (batch x 1024) = network(feats (batch x 1028)); 1 <= batch <= 8192.
+ * Asynchronous. */
+gmgm_status gmgm_ws_forward(gmgm_ctx_t ctx, const float* params, int32_t batch, const float* feats,
+                            float* out);
+
+/* One AdamW step (step >= 1 counts updates) on the masked MSE of a batch.
+ * mask: batch x 1024 per-entry weights or NULL (all ones).  adam_m, adam_v:
+ * optimiser state (param_count floats each, zero before step 1).  loss_out:
+ * host or NULL (then asynchronous; else synchronises): the loss before the
+ * update.  grad_out: device or NULL: the gradient (param_count floats). */
+gmgm_status gmgm_ws_train_step(gmgm_ctx_t ctx, float* params, float* adam_m, float* adam_v, int64_t step,
+                               int32_t batch, const float* feats, const float* target, const float* mask,
+                               float lr, float weight_decay, double* loss_out, float* grad_out);
+
+/* Warm-start eigenvalues from one output row: index i of an axis of rank r
+ * reads the curve at u_i = (i + 1/2) 512 / r - 1/2 (clamped, linear), and
+ * lambda_i = exp(curve(u_i)) / E_i.  Asynchronous. */
+gmgm_status gmgm_ws_apply(gmgm_ctx_t ctx, const float* curves, const double* Ec, int64_t rc,
+                          const double* Eg, int64_t rg, double* lam_c, double* lam_g);
 
 #ifdef __cplusplus
 }

@@ -265,58 +265,76 @@ class SolveResult:
     n_pinned: list
 
 
+STEP_SHRINK = 64.0
+
+
 def solve_eigs(prob: Problem, warm=None, tol: float = 1e-12, max_iter: int = 200) -> SolveResult:
-    """Projected Newton from the cold start 1/E (or a warm start projected onto gauge and box)."""
+    """Projected Newton from the cold start 1/E, or from a warm start (moved to the
+    gauge and clipped to the box) when its NLL is not above the cold start's.
+
+    The minimiser does not depend on the path.  Along flat directions the NLL is
+    constant: steps may drift along them, and the result is moved back to the
+    start's gauge at the end."""
     flats = flat_directions(prob)
-    if warm is None:
-        lam = cold_start(prob)
-    else:
-        lam = _fix_gauge([np.asarray(w, dtype=np.float64).copy() for w in warm], prob, flats)
-        lam = [np.maximum(l, eps) for l, eps in zip(lam, prob.eps)]
+    lam = cold_start(prob)
+    if warm is not None:
+        # a supplied start is used when it is at least as good as 1/E
+        w = _fix_gauge([np.asarray(x, dtype=np.float64).copy() for x in warm], prob, flats)
+        w = [np.maximum(l, eps) for l, eps in zip(w, prob.eps)]
+        if nll(w, prob) <= nll(lam, prob):
+            lam = w
     eps = prob.eps
     it = 0
     g = grad(lam, prob)
     kkt = kkt_residual(lam, g, prob)
-    while kkt > tol and it < max_iter:
-        it += 1
-        f0 = nll(lam, prob)
-        diag, _ = hess_parts(lam, prob)
-        # coordinates within a diagonal-Newton step of their bound that want to go down
-        active = []
-        for l in range(prob.n_axes):
-            reach = np.minimum(1e-3 * lam[l], g[l] / diag[l])
-            active.append((lam[l] - eps[l] <= reach) & (g[l] > 0))
-        free = [~a for a in active]
-        rho = min(1e-2, kkt)
-        d = newton_direction(lam, g, free, prob, rho)
-        for l in range(prob.n_axes):
-            d[l][active[l]] = -g[l][active[l]] / diag[l][active[l]]
-        # never move along a flat direction: the start fixes the gauge there
-        for c in flats:
-            t = _gauge_value(d, c) / sum(prob.ranks[l] * c[l] ** 2 for l in range(prob.n_axes))
+    for _round in range(3):
+        stalled = False
+        while kkt > tol and it < max_iter:
+            it += 1
+            f0 = nll(lam, prob)
+            diag, _ = hess_parts(lam, prob)
+            # coordinates within a diagonal-Newton step of their bound that want to go down
+            active = []
             for l in range(prob.n_axes):
-                d[l] = d[l] - t * c[l]
-        alpha = 1.0
-        accepted = False
-        for _ in range(60):
-            trial = [np.maximum(lam[l] + alpha * d[l], eps[l]) for l in range(prob.n_axes)]
-            pred = 0.0
+                reach = np.minimum(1e-3 * lam[l], g[l] / diag[l])
+                active.append((lam[l] - eps[l] <= reach) & (g[l] > 0))
+            free = [~a for a in active]
+            rho = min(1e-2, kkt)
+            d = newton_direction(lam, g, free, prob, rho)
             for l in range(prob.n_axes):
-                pred += alpha * float(np.dot(g[l][free[l]], d[l][free[l]]))
-                pred += float(np.dot(g[l][active[l]], trial[l][active[l]] - lam[l][active[l]]))
-            f1 = nll(trial, prob)
-            if f1 <= f0 + 1e-4 * pred or abs(pred) <= 1e-13 * (abs(f0) + 1.0):
-                accepted = True
+                d[l][active[l]] = -g[l][active[l]] / diag[l][active[l]]
+            # floor of the step: an active coordinate may go to its bound, a free one
+            # may shrink by at most STEP_SHRINK per iteration (a coupled Newton step
+            # can overshoot far below the optimum, and recovery from the bound
+            # doubles the value per iteration at best)
+            floor = [np.where(active[l], eps[l], np.maximum(eps[l], lam[l] / STEP_SHRINK))
+                     for l in range(prob.n_axes)]
+            alpha = 1.0
+            accepted = False
+            for _ in range(60):
+                trial = [np.maximum(lam[l] + alpha * d[l], floor[l]) for l in range(prob.n_axes)]
+                pred = 0.0
+                for l in range(prob.n_axes):
+                    pred += alpha * float(np.dot(g[l][free[l]], d[l][free[l]]))
+                    pred += float(np.dot(g[l][active[l]], trial[l][active[l]] - lam[l][active[l]]))
+                f1 = nll(trial, prob)
+                if f1 <= f0 + 1e-4 * pred or abs(pred) <= 1e-13 * (abs(f0) + 1.0):
+                    accepted = True
+                    break
+                alpha *= 0.5
+            if not accepted:
+                stalled = True
                 break
-            alpha *= 0.5
-        if not accepted:
-            break
-        lam = trial
+            lam = trial
+            g = grad(lam, prob)
+            kkt = kkt_residual(lam, g, prob)
+        # back to the start's gauge along the flat directions; resume if that
+        # moved the point off the tolerance (rounding of the shift, the box)
+        lam = [np.maximum(l, e) for l, e in zip(_fix_gauge(lam, prob, flats), eps)]
         g = grad(lam, prob)
         kkt = kkt_residual(lam, g, prob)
-    lam = _fix_gauge(lam, prob, flats)
-    g = grad(lam, prob)
-    kkt = kkt_residual(lam, g, prob)
+        if kkt <= tol or it >= max_iter or stalled or not flats:
+            break
     pinned = [int(np.sum(l <= e * (1 + 1e-12))) for l, e in zip(lam, eps)]
     return SolveResult(lam, it, kkt, kkt <= tol, pinned)
 

@@ -37,7 +37,7 @@ class TopkStats(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("n_flat", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kkt", ctypes.c_double),
+                ("n_flat", ctypes.c_int32), ("warm_used", ctypes.c_int32), ("kkt", ctypes.c_double),
                 ("n_pinned", ctypes.c_int64 * 8), ("eps", ctypes.c_double * 8)]
 
 
@@ -60,6 +60,14 @@ SIGNATURES = {
     "gmgm_gram": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
     "gmgm_eigh_small": (ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.POINTER(_I64)]),
     "gmgm_sketch": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _I64, _P, _I64, _P]),
+    "gmgm_ws_param_count": (_I64, []),
+    "gmgm_ws_init": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
+    "gmgm_ws_features": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.c_double, ctypes.c_double, _P]),
+    "gmgm_ws_targets": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _I64, _P]),
+    "gmgm_ws_forward": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
+    "gmgm_ws_train_step": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, _P, _P, _P, ctypes.c_float,
+                                          ctypes.c_float, ctypes.POINTER(ctypes.c_double), _P]),
+    "gmgm_ws_apply": (ctypes.c_int, [_P, _P, _P, _I64, _P, _I64, _P, _P]),
     "gmgm_solve_eigs": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_P), _I32,
                                        ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(_P), ctypes.c_double, _I32, ctypes.POINTER(_P),
@@ -216,6 +224,7 @@ def solve_eigs(E, modalities, eps=None, warm=None, tol: float = 1e-12, max_iter:
     st = load().gmgm_solve_eigs(c, L, ranks, eptr, len(modalities), mods, epsa, wptr, float(tol),
                                 int(max_iter), optr, ctypes.byref(info))
     d = {"iterations": info.iterations, "converged": bool(info.converged), "n_flat": info.n_flat,
+         "warm_used": bool(info.warm_used),
          "kkt": info.kkt, "n_pinned": list(info.n_pinned[:L]), "eps": list(info.eps[:L])}
     if st == 4 and not raise_on_noconv:
         return SolveResult(out, d)
@@ -281,3 +290,107 @@ def sketch(row_ptr, col, val, n: int, p: int, Vt, evals, r: int, out=None, check
     if check:
         _check(c, load().gmgm_sync(c))
     return U
+
+
+# ---------------------------------------------------------------- learned warm start
+WS_BINS = 512
+WS_IN = 2 * WS_BINS + 4
+WS_OUT = 2 * WS_BINS
+
+
+def ws_param_count() -> int:
+    return int(load().gmgm_ws_param_count())
+
+
+def _f64_vec(t, name):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 1 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous 1-D float64 device tensor")
+
+
+def _f32_dev(t, name, numel=None):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 device tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements")
+
+
+def ws_init(params, seed: int):
+    _f32_dev(params, "params", ws_param_count())
+    c = context(params.device.index)
+    _check(c, load().gmgm_ws_init(c, _ptr(params), int(seed) & 0xFFFFFFFFFFFFFFFF))
+
+
+def ws_features(Ec, Eg, dc: float, dg: float, out=None):
+    """The 1028 features of an axis pair (see gmgm_ws_features)."""
+    import torch
+    _f64_vec(Ec, "Ec")
+    _f64_vec(Eg, "Eg")
+    f = torch.empty(WS_IN, dtype=torch.float32, device=Ec.device) if out is None else out
+    _f32_dev(f, "out", WS_IN)
+    c = context(Ec.device.index)
+    _check(c, load().gmgm_ws_features(c, _ptr(Ec), Ec.numel(), _ptr(Eg), Eg.numel(), float(dc), float(dg), _ptr(f)))
+    return f
+
+
+def ws_targets(Ec, lam_c, Eg, lam_g, out=None):
+    import torch
+    for t, nm in ((Ec, "Ec"), (lam_c, "lam_c"), (Eg, "Eg"), (lam_g, "lam_g")):
+        _f64_vec(t, nm)
+    if lam_c.numel() != Ec.numel() or lam_g.numel() != Eg.numel():
+        raise ValueError("eigenvalue vectors must match their spectra")
+    f = torch.empty(WS_OUT, dtype=torch.float32, device=Ec.device) if out is None else out
+    _f32_dev(f, "out", WS_OUT)
+    c = context(Ec.device.index)
+    _check(c, load().gmgm_ws_targets(c, _ptr(Ec), _ptr(lam_c), Ec.numel(), _ptr(Eg), _ptr(lam_g), Eg.numel(),
+                                     _ptr(f)))
+    return f
+
+
+def ws_forward(params, feats, out=None):
+    import torch
+    _f32_dev(params, "params", ws_param_count())
+    _f32_dev(feats, "feats")
+    B = feats.numel() // WS_IN
+    if feats.numel() != B * WS_IN:
+        raise ValueError("feats must be batch x 1028")
+    y = torch.empty(B, WS_OUT, dtype=torch.float32, device=feats.device) if out is None else out
+    c = context(feats.device.index)
+    _check(c, load().gmgm_ws_forward(c, _ptr(params), B, _ptr(feats), _ptr(y)))
+    return y
+
+
+def ws_train_step(params, m, v, step: int, feats, target, mask=None, lr: float = 1e-3, weight_decay: float = 0.0,
+                  want_loss: bool = True, grad_out=None):
+    """One AdamW step; returns the loss before the update (None if not wanted)."""
+    n = ws_param_count()
+    for t, nm in ((params, "params"), (m, "adam_m"), (v, "adam_v")):
+        _f32_dev(t, nm, n)
+    _f32_dev(feats, "feats")
+    B = feats.numel() // WS_IN
+    _f32_dev(target, "target", B * WS_OUT)
+    if mask is not None:
+        _f32_dev(mask, "mask", B * WS_OUT)
+    if grad_out is not None:
+        _f32_dev(grad_out, "grad_out", n)
+    loss = ctypes.c_double()
+    c = context(feats.device.index)
+    _check(c, load().gmgm_ws_train_step(c, _ptr(params), _ptr(m), _ptr(v), int(step), B, _ptr(feats), _ptr(target),
+                                        _ptr(mask) if mask is not None else None, float(lr), float(weight_decay),
+                                        ctypes.byref(loss) if want_loss else None,
+                                        _ptr(grad_out) if grad_out is not None else None))
+    return loss.value if want_loss else None
+
+
+def ws_apply(curves, Ec, Eg):
+    """Warm-start eigenvalues (lam_c, lam_g) from one 1024-long output row."""
+    import torch
+    _f32_dev(curves, "curves", WS_OUT)
+    _f64_vec(Ec, "Ec")
+    _f64_vec(Eg, "Eg")
+    lc = torch.empty_like(Ec)
+    lg = torch.empty_like(Eg)
+    c = context(Ec.device.index)
+    _check(c, load().gmgm_ws_apply(c, _ptr(curves), _ptr(Ec), Ec.numel(), _ptr(Eg), Eg.numel(), _ptr(lc), _ptr(lg)))
+    return lc, lg

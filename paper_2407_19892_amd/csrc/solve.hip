@@ -14,9 +14,10 @@
 // a Schur complement: "hub" axes (a minimum-rank vertex cover of the modality
 // graph) stay, the other axes have diagonal Hessian blocks and are
 // eliminated; the hub system is factored by a one-workgroup Cholesky.
-// Directions that shift whole axes with zero NLL slope (balanced problems)
-// are projected out of every step, and the result is normalised to the gauge
-// of the start 1/E.  Reductions are deterministic (fixed order, compensated).
+// Along directions that shift whole axes with zero NLL slope (balanced
+// problems) the NLL is constant; the result is moved to the gauge of the start
+// 1/E.  A warm start is used when its NLL is not above that of 1/E.
+// Reductions are deterministic (fixed order, compensated).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -288,11 +289,18 @@ __global__ void __launch_bounds__(RED_THREADS) max_kernel(const double* __restri
   }
 }
 
-// Trial point t = max(x + alpha d, eps) of one axis.
-__global__ void trial_kernel(const double* __restrict__ x, const double* __restrict__ d, int n,
-                             double alpha, double eps, double* __restrict__ t) {
+// Trial point t = max(x + alpha d, floor) of one axis: an active coordinate may
+// reach its bound, a free one may shrink by at most STEP_SHRINK per iteration (a
+// coupled Newton step can overshoot far below the optimum, and recovery from
+// the bound doubles the value per iteration at best).
+constexpr double STEP_SHRINK = 64.0;
+__global__ void trial_kernel(const double* __restrict__ x, const double* __restrict__ d,
+                             const int* __restrict__ act, int n, double alpha, double eps,
+                             double* __restrict__ t) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) t[i] = fmax(x[i] + alpha * d[i], eps);
+  if (i >= n) return;
+  const double fl = act[i] ? eps : fmax(eps, x[i] / STEP_SHRINK);
+  t[i] = fmax(x[i] + alpha * d[i], fl);
 }
 
 // Armijo prediction: alpha sum_free g d + sum_active g (t - x)   (one workgroup)
@@ -694,47 +702,63 @@ extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64
   for (int l = 0; l < n_axes; ++l)
     hipLaunchKernelGGL(clip_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.lam + sv.ax[l].off,
                        sv.ax[l].eps, sv.ax[l].r);
+  bool warm_used = false;
+  if (warm) {
+    // a supplied start is used when its NLL is not above that of 1/E (held in trial)
+    double f_warm, f_cold;
+    GMGM_TRY(sv.nll(sv.lam, &f_warm));
+    GMGM_TRY(sv.nll(sv.trial, &f_cold));
+    warm_used = f_warm <= f_cold;
+    if (!warm_used)
+      GMGM_HIP(c, hipMemcpyAsync(sv.lam, sv.trial, T * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
 
   double kres = 0;
   GMGM_TRY(sv.gradient(sv.lam, &kres));
   int it = 0;
   bool stalled = false;
-  while (kres > tol && it < max_iter) {
-    it++;
-    double f0;
-    GMGM_TRY(sv.nll(sv.lam, &f0));
-    GMGM_TRY(sv.direction(std::min(1e-2, kres)));
-    for (auto& cdir : flats) {          // never move along a flat direction
-      double gv;
-      GMGM_TRY(sv.gauge_value(sv.d, cdir, &gv));
-      sv.shift(sv.d, cdir, -gv);
-    }
-    double alpha = 1.0;
-    bool accepted = false;
-    for (int ls = 0; ls < 60; ++ls) {
-      for (int l = 0; l < n_axes; ++l)
-        hipLaunchKernelGGL(trial_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.lam + sv.ax[l].off,
-                           sv.d + sv.ax[l].off, sv.ax[l].r, alpha, sv.ax[l].eps, sv.trial + sv.ax[l].off);
-      hipLaunchKernelGGL(pred_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.g, sv.d, sv.lam, sv.trial,
-                         sv.act, (int)T, alpha, sv.scal + 2);
-      double pred, f1;
-      GMGM_TRY(sv.fetch(&pred, sv.scal + 2, 1));
-      GMGM_TRY(sv.nll(sv.trial, &f1));
-      if (f1 <= f0 + 1e-4 * pred || std::fabs(pred) <= 1e-13 * (std::fabs(f0) + 1.0)) {
-        accepted = true;
+  for (int round = 0; round < 3; ++round) {
+    stalled = false;
+    while (kres > tol && it < max_iter) {
+      it++;
+      double f0;
+      GMGM_TRY(sv.nll(sv.lam, &f0));
+      // steps may drift along flat directions (the NLL is constant there)
+      GMGM_TRY(sv.direction(std::min(1e-2, kres)));
+      double alpha = 1.0;
+      bool accepted = false;
+      for (int ls = 0; ls < 60; ++ls) {
+        for (int l = 0; l < n_axes; ++l)
+          hipLaunchKernelGGL(trial_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.lam + sv.ax[l].off,
+                             sv.d + sv.ax[l].off, sv.act + sv.ax[l].off, sv.ax[l].r, alpha, sv.ax[l].eps,
+                             sv.trial + sv.ax[l].off);
+        hipLaunchKernelGGL(pred_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.g, sv.d, sv.lam, sv.trial,
+                           sv.act, (int)T, alpha, sv.scal + 2);
+        double pred, f1;
+        GMGM_TRY(sv.fetch(&pred, sv.scal + 2, 1));
+        GMGM_TRY(sv.nll(sv.trial, &f1));
+        if (f1 <= f0 + 1e-4 * pred || std::fabs(pred) <= 1e-13 * (std::fabs(f0) + 1.0)) {
+          accepted = true;
+          break;
+        }
+        alpha *= 0.5;
+      }
+      if (!accepted) {
+        stalled = true;
         break;
       }
-      alpha *= 0.5;
+      std::swap(sv.lam, sv.trial);
+      GMGM_TRY(sv.gradient(sv.lam, &kres));
     }
-    if (!accepted) {
-      stalled = true;
-      break;
-    }
-    std::swap(sv.lam, sv.trial);
+    // back to the start's gauge along the flat directions; resume if that moved
+    // the point off the tolerance (rounding of the shift, the box)
+    GMGM_TRY(fix_gauge(sv.lam));
+    for (int l = 0; l < n_axes; ++l)
+      hipLaunchKernelGGL(clip_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.lam + sv.ax[l].off,
+                         sv.ax[l].eps, sv.ax[l].r);
     GMGM_TRY(sv.gradient(sv.lam, &kres));
+    if (kres <= tol || it >= max_iter || stalled || flats.empty()) break;
   }
-  GMGM_TRY(fix_gauge(sv.lam));
-  GMGM_TRY(sv.gradient(sv.lam, &kres));
   for (int l = 0; l < n_axes; ++l)
     GMGM_HIP(c, hipMemcpyAsync(lambda_out[l], sv.lam + sv.ax[l].off, sv.ax[l].r * sizeof(double),
                                hipMemcpyDeviceToDevice, st));
@@ -748,6 +772,7 @@ extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64
     info->iterations = it;
     info->converged = kres <= tol;
     info->n_flat = (int32_t)flats.size();
+    info->warm_used = warm_used ? 1 : 0;
     info->kkt = kres;
     for (int l = 0; l < n_axes; ++l) {
       info->n_pinned[l] = (int64_t)np[l];
