@@ -11,6 +11,16 @@ folding, operand repacking, the MFMA sweep, exact rescoring, the exact
 fallback for uncertified rows and the CSR emit.  Inputs (V, psi) are resident
 in HBM before timing starts.  Prints ONE JSON line on stdout; progress goes
 to stderr.
+
+The other steps of the path are timed once each at the same workload's shape
+(reported under "stages", not part of the metric): the gene-axis Gram of a
+1M x 20k 5%-dense CSR, its FP64 eigendecomposition, the cell-axis factor
+(r = 100) and the eigenvalue MLE on the resulting spectra.  The CSR is the
+fast seeded stand-in (same shape, density and log1p value range as the NB
+generator, without its cluster structure).
+
+--profile-run runs one step of the metric path and one 1 GiB device copy (the
+reference kernel for scaling HBM traffic counters) and prints nothing else.
 """
 import argparse
 import json
@@ -24,6 +34,11 @@ if ROOT not in sys.path:
 
 METRIC = "top-k precision rows/s at 1M cells, BF16-MFMA vs FP32, recall ≥0.999"
 PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
+# HBM traffic of the BF16 sweep kernel at this workload, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs scaled by the counters' readings on a 1 GiB copy (factors 2.0 and
+# 1.0); see profiles/recompose_bf16_1M_r100_k10_hbm_counters.md.  Keyed by the
+# kernel instantiation; set to None whenever that kernel changes.
+SWEEP_TRAFFIC_BYTES = {("bf16", 1_000_000, 100, 10): (8453208.6875 * 2.0 + 250000.0) * 1024}
 
 
 def log(*a):
@@ -68,6 +83,87 @@ def cpu_baseline(V, psi, k, budget_s=15.0):
                       f"(FP64 row recomposition + exact top-k), {t_used:.1f} s"}
 
 
+def stages(g, n, p, r, workers):
+    """Gram, eigendecomposition, cell factor and solve at the workload's shape."""
+    import numpy as np
+    import torch
+
+    import synth
+    out = {"input": f"{n} x {p} CSR stand-in, 5% dense, seed 3000", "r": r}
+    t0 = time.perf_counter()
+    rp, col, val = synth.csr_proxy(n, p, 0.05, seed=3000, workers=workers)
+    nnz = int(rp[-1])
+    out["nnz"] = nnz
+    log(f"stages: generated {nnz} nonzeros in {time.perf_counter() - t0:.1f} s")
+    rpd, cd, vd = (torch.from_numpy(a).cuda() for a in (rp, col, val))
+    del rp, col, val
+    G = torch.empty(p, p, dtype=torch.float32, device="cuda")
+
+    def timed(fn, reps):
+        best = None
+        for _ in range(reps):
+            g.sync()
+            g.kernel_times()
+            g.set_timing(True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+            g.set_timing(False)
+            kms, cnt = g.kernel_times()
+            if best is None or wall < best[0]:
+                best = (wall, kms, cnt, res)
+        return best
+
+    g.gram(rpd, cd, vd, n, p, out=G)                      # warm-up
+    wall, kms, cnt, _ = timed(lambda: g.gram(rpd, cd, vd, n, p, out=G), 1)
+    pp = (p + 255) // 256 * 256
+    dense = float(n) * pp * pp                            # 2 n pp^2 / 2: upper tiles incl. diagonal tiles
+    out["gram"] = {"ms": wall * 1e3, "tile_kernel_ms": kms, "launches": cnt, "bound": "mfma",
+                   "unit": "TFLOP/s", "achieved": dense / (kms * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp32"],
+                   "frac": dense / (kms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+                   "flops_per_launch_set": dense, "flops_kind": "dense FP32 MFMA, n * p_pad^2 (symmetric half)"}
+    log(f"stages: gram {wall * 1e3:.1f} ms ({out['gram']['achieved']:.1f} TF/s)")
+    wall, kms, cnt, res = timed(lambda: g.eigh_small(G), 1)
+    w, Vt, rank = res
+    out["eigh"] = {"ms": wall * 1e3, "solver_ms": kms, "p": p, "rank": rank,
+                   "note": "rocSOLVER divide and conquer on an FP64 copy"}
+    log(f"stages: eigh {wall * 1e3:.1f} ms, rank {rank}")
+    U = torch.empty(n, r, dtype=torch.float32, device="cuda")
+    g.sketch(rpd, cd, vd, n, p, Vt, w, r, out=U)
+    wall, kms, cnt, _ = timed(lambda: g.sketch(rpd, cd, vd, n, p, Vt, w, r, out=U), 3)
+    byts = nnz * 8 + (n + 1) * 8 + p * r * (4 + 8) + n * r * 4
+    out["sketch"] = {"ms": wall * 1e3, "kernel_ms": kms, "bound": "hbm", "unit": "GB/s",
+                     "achieved": byts / (kms * 1e-3) / 1e9, "peak": 8000.0,
+                     "frac": byts / (kms * 1e-3) / 1e9 / 8000.0, "algorithmic_bytes": byts}
+    log(f"stages: sketch {wall * 1e3:.2f} ms ({out['sketch']['achieved']:.0f} GB/s)")
+    Ec, Eg = w[:r].contiguous(), w[:rank].contiguous()
+    g.solve_eigs([Ec, Eg], [(0, 1)])
+    t = time.perf_counter()
+    sol = g.solve_eigs([Ec, Eg], [(0, 1)])
+    wall = time.perf_counter() - t
+    out["solve"] = {"ms": wall * 1e3, "r_c": r, "r_g": rank, **{k: sol.info[k] for k in
+                                                            ("iterations", "kkt", "n_pinned")}}
+    log(f"stages: solve {wall * 1e3:.1f} ms, {sol.info['iterations']} iterations")
+    del rpd, cd, vd, G, Vt, U
+    torch.cuda.empty_cache()
+    return out
+
+
+def profile_run(g, Vd, pd, k, prec, n):
+    """One metric step and one 1 GiB device copy (counter calibration)."""
+    import torch
+    out = (torch.empty(n + 1, dtype=torch.int64, device="cuda"), torch.empty(n * k, dtype=torch.int32, device="cuda"),
+           torch.empty(n * k, dtype=torch.float32, device="cuda"))
+    g.recompose_topk(Vd, pd, k, prec=prec, out=out)
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("profile run done")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +176,8 @@ def main():
     ap.add_argument("--compare", default="fp32", help="precisions timed beside the metric")
     ap.add_argument("--compare-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timings")
+    ap.add_argument("--profile-run", action="store_true", help="one step + a 1 GiB copy, no JSON")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -100,6 +198,9 @@ def main():
     V, psi = workload(n, r)
     Vd = torch.from_numpy(V).cuda()
     pd = torch.from_numpy(psi).cuda()
+    if args.profile_run:
+        profile_run(g, Vd, pd, k, args.prec, n)
+        return
 
     def alloc():
         return (torch.empty(n + 1, dtype=torch.int64, device="cuda"),
@@ -141,12 +242,13 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "sweep_kernel",
                      "achieved": flops / (sweep_ms * 1e-3) / 1e12, "peak": PEAK_TFLOPS[args.prec],
                      "unit": "TFLOP/s", "frac": flops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
-                     "traffic": None, "sweep_ms": sweep_ms,
+                     "traffic": SWEEP_TRAFFIC_BYTES.get((args.prec, n, r, k)), "traffic_unit": "bytes",
+                     "sweep_ms": sweep_ms,
                      "algorithmic_flops_per_launch": flops, "executed_mfma_flops": st_main["mfma_flops"]},
         "stats": st_main,
     }
     ref = out_main
-    for prec in [p for p in args.compare.split(",") if p and p != args.prec]:
+    for prec in [p for p in args.compare.split(",") if p in PEAK_TFLOPS and p != args.prec]:
         out = alloc()
         log(f"timing {prec}: {args.compare_steps} steps")
         s, sw, st = run(prec, args.compare_steps, 1, out)
@@ -160,6 +262,10 @@ def main():
     if "fp32" in result:
         result["recall_vs_fp32"] = result["fp32"][f"recall_of_{args.prec}_vs_fp32"]
         result["speedup_vs_fp32"] = result["fp32"]["ms_per_step"] / result["ms_per_step"]
+    if not args.no_stages:
+        del out_main, ref
+        torch.cuda.empty_cache()
+        result["stages"] = stages(g, n, 20_000, r, workers=min(16, os.cpu_count() or 1))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on sampled rows)")
         result["cpu_baseline"] = cpu_baseline(V, psi, k)
