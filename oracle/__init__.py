@@ -21,10 +21,11 @@ from .solver import Problem, nll, grad, solve_eigs, alg1_gradient_descent, defau
 from .recompose import psi_dense, psi_rows, psi_blockwise
 from .topk import topk_row, topk_csr, near_tie_rows
 from . import warmstart
+from . import range_finder
 
 __all__ = [
     "gram_dense", "gram_csr", "eigh_desc", "numerical_rank", "cell_factor",
     "Problem", "nll", "grad", "solve_eigs", "alg1_gradient_descent", "default_eps",
     "psi_dense", "psi_rows", "psi_blockwise", "topk_row", "topk_csr", "near_tie_rows",
-    "warmstart",
+    "warmstart", "range_finder",
 ]
