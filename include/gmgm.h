@@ -181,6 +181,47 @@ gmgm_status gmgm_sketch(gmgm_ctx_t ctx, int64_t n, int64_t p, int64_t nnz, const
                         const int32_t* col, const float* val, const double* evecs, int64_t ldv,
                         const double* evals, int64_t r, float* U);
 
+/* A CSR matrix (all arrays device, caller-owned): row_ptr has n_rows + 1
+ * int64 entries, col and val nnz entries; val NULL means all ones. */
+typedef struct {
+  int64_t n_rows, n_cols, nnz;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const float* val;
+} gmgm_csr;
+
+/* X^T in CSR form (the CSC of X): row_ptr_t (n_cols + 1 int64), col_t (nnz
+ * int32 row indices of X), val_t (nnz FP32; ones when X.val is NULL).  The
+ * order of entries within a transposed row is not fixed.  Asynchronous;
+ * malformed X is reported as GMGM_E_SHAPE by the next synchronising call. */
+gmgm_status gmgm_csr_transpose(gmgm_ctx_t ctx, gmgm_csr X, int64_t* row_ptr_t, int32_t* col_t, float* val_t);
+
+/*
+ * Leading eigenpairs of S = D D^T for an axis shared by several modalities,
+ * D = [X_1 | ... | X_B] (the Notation section's concatenation; S's
+ * eigenvectors are D's left singular vectors, Algorithm 1's first loop), by
+ * randomized subspace iteration (Halko, Martinsson and Tropp 2011):
+ *   Y = D Omega; Q = orth(Y); q times { Q' = orth(D^T Q); Q = orth(D Q') };
+ *   Z = D^T Q; Z^T Z = W diag(theta) W^T (theta descending);
+ *   evals = theta[:r], vecs = Q W[:, :r].
+ * orth() is the thin-QR Q factor with a positive R diagonal (CholeskyQR2).
+ *
+ *   n_blocks    1..16 blocks X_m, each n x p_m (same n).
+ *   blocks      host array of the X_m; blocks_t: host array of their
+ *               transposes (p_m x n, e.g. from gmgm_csr_transpose).
+ *   omega       (sum p_m) x k FP64 row-major test matrix (device).
+ *   k           subspace width, 1..128, k <= min(n, sum p_m); q: 0..64.
+ *   r           1..k eigenpairs returned.
+ *   evals       r FP64 (device), descending.
+ *   vecs        n x r FP32 row-major (device), orthonormal columns.
+ * Sparse products are this library's FP64-accumulating kernels; the k-wide
+ * dense steps use rocBLAS (dgemm, dtrsm) and rocSOLVER (dpotrf, dsyevd).
+ * Synchronises.  GMGM_E_NOCONV if a basis is numerically rank deficient.
+ */
+gmgm_status gmgm_subspace_eig(gmgm_ctx_t ctx, int32_t n_blocks, const gmgm_csr* blocks,
+                              const gmgm_csr* blocks_t, const double* omega, int64_t k, int32_t q,
+                              int64_t r, double* evals, float* vecs);
+
 /* Result of one gmgm_solve_eigs call. */
 typedef struct {
   int32_t iterations;       /* Newton iterations taken */

@@ -35,6 +35,11 @@ class TopkStats(ctypes.Structure):
                 ("mfma_flops", ctypes.c_double)]
 
 
+class Csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("n_flat", ctypes.c_int32), ("warm_used", ctypes.c_int32), ("kkt", ctypes.c_double),
@@ -68,6 +73,9 @@ SIGNATURES = {
     "gmgm_ws_train_step": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, _P, _P, _P, ctypes.c_float,
                                           ctypes.c_float, ctypes.POINTER(ctypes.c_double), _P]),
     "gmgm_ws_apply": (ctypes.c_int, [_P, _P, _P, _I64, _P, _I64, _P, _P]),
+    "gmgm_csr_transpose": (ctypes.c_int, [_P, Csr, _P, _P, _P]),
+    "gmgm_subspace_eig": (ctypes.c_int, [_P, _I32, ctypes.POINTER(Csr), ctypes.POINTER(Csr), _P, _I64, _I32, _I64,
+                                         _P, _P]),
     "gmgm_solve_eigs": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_P), _I32,
                                        ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(_P), ctypes.c_double, _I32, ctypes.POINTER(_P),
@@ -394,3 +402,59 @@ def ws_apply(curves, Ec, Eg):
     c = context(Ec.device.index)
     _check(c, load().gmgm_ws_apply(c, _ptr(curves), _ptr(Ec), Ec.numel(), _ptr(Eg), Eg.numel(), _ptr(lc), _ptr(lg)))
     return lc, lg
+
+
+
+# ---------------------------------------------------------------- shared large axis
+class CsrMatrix:
+    """A device CSR matrix (row_ptr int64, col int32, val float32 or None)."""
+
+    def __init__(self, row_ptr, col, val, n_rows: int, n_cols: int):
+        _csr_args(row_ptr, col, val, n_rows)
+        self.row_ptr, self.col, self.val = row_ptr, col, val
+        self.n_rows, self.n_cols = int(n_rows), int(n_cols)
+
+    @property
+    def nnz(self):
+        return self.col.numel()
+
+    def c_struct(self):
+        return Csr(self.n_rows, self.n_cols, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                   self.val.data_ptr() if self.val is not None else None)
+
+    def transpose(self):
+        """X^T as a CsrMatrix (see gmgm_csr_transpose)."""
+        import torch
+        dev = self.row_ptr.device
+        rp = torch.empty(self.n_cols + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+        val = torch.empty(self.nnz, dtype=torch.float32, device=dev)
+        c = context(dev.index)
+        _check(c, load().gmgm_csr_transpose(c, self.c_struct(), _ptr(rp), _ptr(col), _ptr(val)))
+        _check(c, load().gmgm_sync(c))
+        return CsrMatrix(rp, col, val, self.n_cols, self.n_rows)
+
+
+def subspace_eig(blocks, omega, q: int, r: int, blocks_t=None):
+    """(evals (r, FP64), vecs (n x r, FP32)) of D D^T, D = [X_1 | ...] (see
+    gmgm_subspace_eig).  blocks: list of CsrMatrix sharing n_rows; omega:
+    (sum p_m) x k FP64 device tensor; blocks_t: their transposes (built when None)."""
+    import torch
+    if blocks_t is None:
+        blocks_t = [b.transpose() for b in blocks]
+    if not (omega.is_cuda and omega.dtype == torch.float64 and omega.dim() == 2 and omega.is_contiguous()):
+        raise TypeError("omega must be a contiguous 2-D float64 device tensor")
+    P = sum(b.n_cols for b in blocks)
+    if omega.shape[0] != P:
+        raise ValueError(f"omega must have {P} rows")
+    k = omega.shape[1]
+    n = blocks[0].n_rows
+    dev = omega.device
+    evals = torch.empty(r, dtype=torch.float64, device=dev)
+    vecs = torch.empty(n, r, dtype=torch.float32, device=dev)
+    B = (Csr * len(blocks))(*[b.c_struct() for b in blocks])
+    BT = (Csr * len(blocks))(*[b.c_struct() for b in blocks_t])
+    c = context(dev.index)
+    _check(c, load().gmgm_subspace_eig(c, len(blocks), B, BT, _ptr(omega), k, int(q), int(r), _ptr(evals),
+                                       _ptr(vecs)))
+    return evals, vecs
