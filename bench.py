@@ -15,7 +15,9 @@ to stderr.
 The other steps of the path are timed once each at the same workload's shape
 (reported under "stages", not part of the metric): the gene-axis Gram of a
 1M x 20k 5%-dense CSR, its FP64 eigendecomposition, the cell-axis factor
-(r = 100) and the eigenvalue MLE on the resulting spectra.  The CSR is the
+(r = 100), the eigenvalue MLE on the resulting spectra, and the shared-cell
+path with 1M x 50k binary peaks at 2% (transposes, subspace iteration for
+cells and peaks with k = 110, q = 2, the three-axis solve).  The CSR is the
 fast seeded stand-in (same shape, density and log1p value range as the NB
 generator, without its cluster structure).
 
@@ -83,7 +85,7 @@ def cpu_baseline(V, psi, k, budget_s=15.0):
                       f"(FP64 row recomposition + exact top-k), {t_used:.1f} s"}
 
 
-def stages(g, n, p, r, workers):
+def stages(g, n, p, r, workers, multimodal=True):
     """Gram, eigendecomposition, cell factor and solve at the workload's shape."""
     import numpy as np
     import torch
@@ -146,9 +148,60 @@ def stages(g, n, p, r, workers):
     out["solve"] = {"ms": wall * 1e3, "r_c": r, "r_g": rank, **{k: sol.info[k] for k in
                                                             ("iterations", "kkt", "n_pinned")}}
     log(f"stages: solve {wall * 1e3:.1f} ms, {sol.info['iterations']} iterations")
-    del rpd, cd, vd, G, Vt, U
+    del G, Vt, U
+    torch.cuda.empty_cache()
+    if multimodal:
+        out["shared_cells"] = shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, workers)
+    del rpd, cd, vd
     torch.cuda.empty_cache()
     return out
+
+
+def shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, workers, p_pk=50_000, k_over=10, q=2):
+    """Cells shared by RNA (the CSR above) and binary ATAC peaks (1M x 50k, 2%):
+    subspace iteration for cells on [X_rna | X_pk] and for peaks on X_pk^T, then
+    the three-axis solve."""
+    import numpy as np
+    import torch
+
+    import synth
+    t0 = time.perf_counter()
+    prp, pcol, _ = synth.csr_proxy(n, p_pk, 0.02, seed=4000, workers=workers)
+    log(f"stages: peaks generated, {int(prp[-1])} nonzeros in {time.perf_counter() - t0:.1f} s")
+    rna = g.CsrMatrix(rpd, cd, vd, n, p)
+    pk = g.CsrMatrix(torch.from_numpy(prp).cuda(), torch.from_numpy(pcol).cuda(), None, n, p_pk)
+    del prp, pcol
+    res = {"input": f"RNA {n} x {p} ({nnz} nonzeros) + binary peaks {n} x {p_pk} at 2% "
+                    f"({pk.nnz} nonzeros), seeds 3000 / 4000", "k": r + k_over, "q": q}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rna_t, pk_t = rna.transpose(), pk.transpose()
+    torch.cuda.synchronize()
+    res["transpose_ms"] = (time.perf_counter() - t) * 1e3
+    gen = torch.Generator(device="cuda").manual_seed(4001)
+    k = r + k_over
+    om_c = torch.randn(p + p_pk, k, dtype=torch.float64, device="cuda", generator=gen)
+    om_p = torch.randn(n, k, dtype=torch.float64, device="cuda", generator=gen)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Ec, Vc = g.subspace_eig([rna, pk], om_c, q, r, blocks_t=[rna_t, pk_t])
+    torch.cuda.synchronize()
+    res["cells_subspace_ms"] = (time.perf_counter() - t) * 1e3
+    t = time.perf_counter()
+    Ep, Vp = g.subspace_eig([pk_t], om_p, q, r, blocks_t=[pk])
+    torch.cuda.synchronize()
+    res["peaks_subspace_ms"] = (time.perf_counter() - t) * 1e3
+    # sparse work of one subspace run: (2q + 2) products over all nonzeros, k FP64 FMAs each
+    res["cells_sparse_flops"] = float(2 * (2 * q + 2) * (nnz + pk.nnz) * k)
+    t = time.perf_counter()
+    sol = g.solve_eigs([Ec, Eg, Ep], [(0, 1), (0, 2)])
+    res["solve_ms"] = (time.perf_counter() - t) * 1e3
+    res["solve"] = {kk: sol.info[kk] for kk in ("iterations", "kkt", "n_pinned")}
+    log(f"stages: shared cells: transposes {res['transpose_ms']:.0f} ms, cells {res['cells_subspace_ms']:.0f} ms, "
+        f"peaks {res['peaks_subspace_ms']:.0f} ms, solve {res['solve_ms']:.0f} ms")
+    del rna_t, pk_t, pk, om_c, om_p, Vc, Vp
+    torch.cuda.empty_cache()
+    return res
 
 
 def profile_run(g, Vd, pd, k, prec, n):
@@ -177,6 +230,7 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timings")
+    ap.add_argument("--no-multimodal", action="store_true", help="skip the shared-cell-axis stage")
     ap.add_argument("--profile-run", action="store_true", help="one step + a 1 GiB copy, no JSON")
     args = ap.parse_args()
 
@@ -265,7 +319,8 @@ def main():
     if not args.no_stages:
         del out_main, ref
         torch.cuda.empty_cache()
-        result["stages"] = stages(g, n, 20_000, r, workers=min(16, os.cpu_count() or 1))
+        result["stages"] = stages(g, n, 20_000, r, workers=min(16, os.cpu_count() or 1),
+                                  multimodal=not args.no_multimodal)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on sampled rows)")
         result["cpu_baseline"] = cpu_baseline(V, psi, k)
