@@ -97,7 +97,7 @@ typedef struct {
  *   keep the k columns j != i with the largest |Psi_ij| (ties to smaller j),
  * without forming Psi.
  *
- *   n, r        V is n x r, row-major FP32 (device).  1 <= r <= 128.
+ *   n, r        V is n x r, row-major FP32 (device).  2 <= n <= 2^31 - 64, 1 <= r <= 128.
  *   psi         r FP64 eigenvalues (device).
  *   row_begin, row_end   0 <= row_begin < row_end <= n.
  *   k           1 <= k <= 24 and k <= n - 1.

@@ -250,12 +250,18 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
 
   for (int q = lane; q < a.r; q += 64) wrow[wave][q] = (double)a.V[i * a.r + q] * a.psi[q];
 
-  float mout = -1.0f;
+  const double vmax = (double)__uint_as_float(*a.vmax_bits);
+  const double beta = a.cprec * a.wnorm[i - a.w_lo] * vmax;
+  // the largest value a sweep list may have dropped: its C-th entry when full,
+  // and its k-th entry - 2 beta (the sweep's threshold never exceeds either)
+  double mout = -1.0;
   for (int q = lane; q < a.S * a.nsub; q += 64) {
-    const int64_t e = cbase + (int64_t)q * a.C + a.C - 1;
-    if (a.cidx[e] != INVALID_J) mout = fmaxf(mout, a.cval[e]);
+    const int64_t e = cbase + (int64_t)q * a.C;
+    if (a.cidx[e + a.C - 1] != INVALID_J) mout = fmax(mout, (double)a.cval[e + a.C - 1]);
+    if (a.cidx[e + a.k - 1] != INVALID_J)
+      mout = fmax(mout, (double)(a.cval[e + a.k - 1] - (float)(2.0 * beta)));
   }
-  mout = wave_max_f32(mout);
+  mout = wave_max_f64(mout);
 
   // k-th largest approximate key among the candidates
   int nvalid = 0;
@@ -277,8 +283,6 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
     found++;
   }
   const float ak = found == a.k ? __uint_as_float((unsigned)(prev >> 32)) : -1.0f;
-  const double vmax = (double)__uint_as_float(*a.vmax_bits);
-  const double beta = a.cprec * a.wnorm[i - a.w_lo] * vmax;
   const double thr = (double)ak - 2.0 * beta;
 
   // rescoring set R, compacted into LDS
@@ -348,7 +352,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
   double tk = 0.0;
   if (ok) {
     tk = fabs(sel_v[wave][a.k - 1]);
-    if (mout >= 0.0f) ok = (double)mout + beta < tk;
+    if (mout >= 0.0) ok = mout + beta < tk;
   }
   if (lane == 0) {
     atomicAdd(&a.counters[0], (unsigned long long)nvalid);
@@ -567,7 +571,7 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
   GMGM_CHECK_CTX(c);
   const int prec = (int)prec_e;
   if (prec < 0 || prec > 2) return set_err(c, GMGM_E_ARG, "unknown precision %d", prec);
-  if (n < 2 || n > 0x7ffffff0LL) return set_err(c, GMGM_E_SHAPE, "n = %lld out of range", (long long)n);
+  if (n < 2 || n > 0x7fffffc0LL) return set_err(c, GMGM_E_SHAPE, "n = %lld out of range [2, 2^31 - 64]", (long long)n);
   if (r < 1 || r > 128) return set_err(c, GMGM_E_SHAPE, "r = %lld must be in [1, 128]", (long long)r);
   if (row_begin < 0 || row_end > n || row_begin >= row_end)
     return set_err(c, GMGM_E_SHAPE, "row range [%lld, %lld) invalid for n = %lld",
@@ -661,6 +665,11 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
   sa.row_end = row_end;
   sa.S = S;
   sa.tiles_per_split = tps;
+  sa.wnorm = wnorm;
+  sa.vmax_bits = vmax_bits;
+  sa.w_lo = w_lo;
+  sa.cprec = cprec_for(prec, kpad);
+  sa.k = k;
   hipEvent_t t0 = timing_start(c);
   sweep<<<dim3((unsigned)gx, (unsigned)S), dim3(SW_THREADS), 0, st>>>(sa);
   timing_stop(c, t0);
@@ -737,6 +746,7 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
     sb.n_wtiles = (int)wtB;
     sb.S = SB;
     sb.tiles_per_split = tpsB;
+    sb.cprec = cprec_for(P_F32, kpadB);
     sweepB<<<dim3((unsigned)gxB, (unsigned)SB), dim3(SW_THREADS), 0, st>>>(sb);
     FinalArgs fb = fa;
     fb.cval = B.cval;

@@ -9,9 +9,17 @@
 // 32x32 MFMA tile a lane holds 16 values of one row of Psi (the accumulator
 // column is the lane).  Each lane keeps a sorted top-C list (approximate
 // |Psi_ij|, ascending j, ties to smaller j) of the row it owns and tests a
-// whole tile against the list's last entry with one max and one compare;
-// values above it are appended to a per-lane LDS queue that is merged into
-// the list (all lanes in parallel) only when some lane's queue fills.
+// whole tile against a threshold with one max and one compare.  The threshold
+// is max(list's C-th value, list's k-th value - 2 beta_i), beta_i the row's
+// rounding bound: a value below it can neither enter the list's top C nor come
+// within 2 beta_i of the final k-th, so the final certificate (which takes the
+// same maximum over the dropped values) still holds.
+// Tiles where some lane has a value above it take the slow path: with two row
+// tiles per wave the two accumulators' lane halves are exchanged so that every
+// lane holds the 32 values of its own row, the values above the threshold are
+// appended to the lane's own LDS queue (entry-major, lane-minor: no bank
+// conflicts), and the queues are merged into the lists (all lanes at once)
+// only when some lane's queue could overflow.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,6 +50,12 @@ struct SweepArgs {
   int64_t row0;           // contiguous mode: global row of local row 0
   int64_t row_begin, row_end;   // contiguous mode: rows whose lists are written
   int S, tiles_per_split;
+  // per-row rounding bound beta_i = cprec ||W_i|| max_j ||V_j|| (rows from w_lo)
+  const double* wnorm;
+  const unsigned* vmax_bits;
+  int64_t w_lo;
+  double cprec;
+  int k;
 };
 
 template <int PREC>
@@ -67,20 +81,22 @@ __device__ inline v16f mfma_chunk(const u32x4* a, const u32x4* b, v16f acc, int 
 
 // Insert (v, j) into the descending list (lv, li) of length C; requires v > lv[C-1].
 // Equal values keep their order, so with ascending j per lane ties go to smaller j.
+// One downward pass: entry s takes entry s-1 when v beats entry s-1, v when v
+// beats entry s only, else stays; only two comparison masks are live at a time.
 template <int C>
 __device__ inline void list_insert(float (&lv)[C], int (&li)[C], float v, int j) {
-  bool gt[C];
-#pragma unroll
-  for (int s = 0; s < C; ++s) gt[s] = v > lv[s];
+  bool g_hi = v > lv[C - 1];
 #pragma unroll
   for (int s = C - 1; s > 0; --s) {
-    float nv = gt[s - 1] ? lv[s - 1] : (gt[s] ? v : lv[s]);
-    int nj = gt[s - 1] ? li[s - 1] : (gt[s] ? j : li[s]);
+    const bool g_lo = v > lv[s - 1];       // entry s-1 is not yet updated
+    const float nv = g_lo ? lv[s - 1] : (g_hi ? v : lv[s]);
+    const int nj = g_lo ? li[s - 1] : (g_hi ? j : li[s]);
     lv[s] = nv;
     li[s] = nj;
+    g_hi = g_lo;
   }
-  lv[0] = gt[0] ? v : lv[0];
-  li[0] = gt[0] ? j : li[0];
+  lv[0] = g_hi ? v : lv[0];
+  li[0] = g_hi ? j : li[0];
 }
 
 // Lane halves: after a 32x32 MFMA, lanes l and l + 32 hold the two halves
@@ -105,7 +121,8 @@ __host__ __device__ constexpr bool sweep_pairs(int TI) { return TI == 2; }
 __host__ __device__ constexpr int sweep_nsub(int TI) { return sweep_pairs(TI) ? 1 : 2; }
 // V tiles per LDS stage: about 28 KB per stage buffer.
 __host__ __device__ constexpr int sweep_tps(int UNITS) { return 28 / UNITS > 0 ? 28 / UNITS : 1; }
-constexpr int SW_Q = 8;   // append-queue entries per (list, writer half), in LDS
+constexpr int SW_Q = 16;  // append-queue entries per lane (own list), in LDS
+static_assert(SW_Q >= 16, "the slow path appends up to 16 values per half row after a flush");
 
 struct QEntry {
   float v;
@@ -122,8 +139,8 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   constexpr int STAGE_U = TPS * TILE_U;           // chunks per stage
   constexpr int PF = (STAGE_U + SW_THREADS - 1) / SW_THREADS;
   __shared__ u32x4 lds[2][STAGE_U];
-  // queue[wave][owner lane][writer half][entry]
-  __shared__ QEntry queue[SW_WAVES][64][2][SW_Q];
+  // queue[wave][entry][lane]: each lane appends to its own column
+  __shared__ QEntry queue[SW_WAVES][SW_Q][64];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -139,8 +156,10 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   const bool active = wt0 < n_wt;                 // wave-uniform; idle waves still stage V
 
   u32x4 b[TI][UNITS];
-  int64_t myrow[TI];                              // global row of this lane's values (-1: none)
-  int64_t slot[TI];                               // candidate slot (-1: not written)
+  // 32-bit indices throughout (the host guarantees n < 2^31 - 64)
+  const int n32 = (int)a.n;
+  int myrow[TI];                                  // global row of this lane's values (-1: none)
+  int slot[TI];                                   // candidate slot (-1: not written)
   int ewt[TI];
 #pragma unroll
   for (int t = 0; t < TI; ++t) {
@@ -156,11 +175,11 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
       if (listed) {
         if (w < nrows_list) {
           myrow[t] = a.row_list[w];
-          slot[t] = w;
+          slot[t] = (int)w;
         }
       } else {
-        myrow[t] = a.row0 + w;
-        if (myrow[t] >= a.row_begin && myrow[t] < a.row_end) slot[t] = myrow[t] - a.row_begin;
+        myrow[t] = (int)(a.row0 + w);
+        if (myrow[t] >= a.row_begin && myrow[t] < a.row_end) slot[t] = (int)(myrow[t] - a.row_begin);
       }
     } else {
 #pragma unroll
@@ -178,55 +197,46 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
     lv[s] = -1.0f;
     li[s] = INVALID_J;
   }
-  float tau[TI];       // last entry of the list that tile t's values of this lane go to
-  int cnt[TI];         // entries this lane queued for that list
+  float tau[TI];       // threshold of the list of the row whose values this lane holds in tile t
 #pragma unroll
-  for (int t = 0; t < TI; ++t) {
-    tau[t] = -1.0f;
-    cnt[t] = 0;
-  }
-  // owner lane of the list that tile t's values of this lane go to
-  auto owner = [&](int t) { return PAIR ? l32 + 32 * t : lane; };
+  for (int t = 0; t < TI; ++t) tau[t] = -1.0f;
+  int cnt = 0;         // entries in this lane's queue
+  // the row of this lane's own list: row l32 of tile h (pairs) or of the lane's tile
+  const int myrow_own = PAIR ? myrow[h == 0 ? 0 : TI - 1] : myrow[0];
+  const int ew_own = PAIR ? ewt[h == 0 ? 0 : TI - 1] : ewt[0];
+  // 2 beta of the own row (0 for lanes without a row)
+  const float beta2 = myrow_own >= 0
+      ? (float)(2.0 * a.cprec * a.wnorm[myrow_own - a.w_lo] * (double)__uint_as_float(*a.vmax_bits))
+      : 0.0f;
+  float own_tau = -1.0f;   // max(lv[C-1], lv[k-1] - beta2), refreshed by flush
 
-  // Merge every queue of the wave into its owner's list (all lanes at once),
-  // then refresh the cached thresholds.  Wave-uniform.
+  // Merge every lane's queue into its list (all lanes at once), then refresh the
+  // cached thresholds.  Wave-uniform.  A lane reads only the entries it wrote,
+  // and a wave's LDS operations complete in order.
   auto flush = [&]() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    int c0, c1;
-    if constexpr (PAIR) {
-      c0 = cnt[0];
-      c1 = cnt[TI - 1];
-      swap_halves(c0, c1);       // owner's queues: c0 from writer half 0, c1 from half 1
-    } else {
-      c0 = cnt[0];
-      c1 = 0;
-    }
-    int maxc = max(c0, c1);
+    int maxc = cnt;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) maxc = max(maxc, __shfl_xor(maxc, off, 64));
     for (int q = 0; q < maxc; ++q) {
-      if (q < c0) {
-        const QEntry e = queue[wave][lane][0][q];
-        if (e.v > lv[C - 1]) list_insert<C>(lv, li, e.v, e.j);
-      }
-      if (PAIR && q < c1) {
-        const QEntry e = queue[wave][lane][1][q];
+      if (q < cnt) {
+        const QEntry e = queue[wave][q][lane];
         if (e.v > lv[C - 1]) list_insert<C>(lv, li, e.v, e.j);
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    cnt = 0;
+    // the k-th entry of the descending list: the minimum of its first k entries
+    // (a minimum rather than an index keeps the list in registers)
+    float kth = lv[0];
 #pragma unroll
-    for (int t = 0; t < TI; ++t) cnt[t] = 0;
+    for (int q = 1; q < C; ++q) kth = q < a.k ? fminf(kth, lv[q]) : kth;
+    own_tau = fmaxf(lv[C - 1], kth - beta2);
     if constexpr (PAIR) {
-      float x = lv[C - 1], y = lv[C - 1];
+      float x = own_tau, y = own_tau;
       swap_halves(x, y);         // x: list of row l32 of tile 0, y: of tile 1
       tau[0] = x;
       tau[TI - 1] = y;
     } else {
-      tau[0] = lv[C - 1];
+      tau[0] = own_tau;
     }
   };
 
@@ -281,9 +291,14 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
         for (int u = 0; u < UNITS; ++u)
 #pragma unroll
           for (int t = 0; t < TI; ++t) acc[t] = mfma_chunk<PREC>(av, b[t], acc[t], u);
+        // issue every operand read of the tile before its MFMAs (else the
+        // scheduler reuses one register and waits on each read in turn)
+        __builtin_amdgcn_sched_group_barrier(0x100, UNITS, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, UNITS * TI * (PREC == P_F32 ? 4 : 1) / (PREC == P_FP8 ? 2 : 1), 0);
 
-        const int64_t j0 = (int64_t)jt * 32;
-        bool masked = j0 + 32 > a.n;               // wave-uniform
+        const int j0 = jt * 32;
+        // tiles holding the diagonal or the end of the columns exclude some values
+        bool masked = j0 + 32 > n32;               // wave-uniform
         if (listed) {
           bool diag = false;
 #pragma unroll
@@ -292,6 +307,7 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
         } else {
           masked = masked || (jt >= tile0 && jt < tile0 + TI);
         }
+        const int lim = n32 - j0;                  // columns at offsets >= lim do not exist
         int evt = 0;
         if constexpr (PREC == P_FP8) evt = a.ev[jt];
 
@@ -302,11 +318,12 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
         for (int t = 0; t < TI; ++t) {
           float mm;
           if (masked) {
+            const int d = myrow[t] - j0;           // the diagonal's offset in this tile
             mm = -1.0f;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-              const int64_t j = j0 + acc_row(v, h);
-              mm = fmaxf(mm, (j < a.n && j != myrow[t]) ? fabsf(acc[t][v]) : -1.0f);
+              const int o = acc_row(v, h);
+              mm = fmaxf(mm, (o < lim && o != d) ? fabsf(acc[t][v]) : -1.0f);
             }
           } else {
             mm = fabsf(acc[t][0]);
@@ -320,40 +337,62 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
           any |= pass[t];
         }
         if (__ballot(any)) {
+          // own-row values: with two row tiles, exchange the accumulators' lane
+          // halves so that acc[0] / acc[1] hold columns acc_row(v, 0) / acc_row(v, 1)
+          // of this lane's own row; with one tile, acc[0] holds half h of it
+          if constexpr (PAIR) {
 #pragma unroll
-          for (int t = 0; t < TI; ++t) {
-            if (!__ballot(pass[t])) continue;
-            // groups of 4 values (4 consecutive columns); queue the values above
-            // the threshold of the groups that have any, without branches per value
+            for (int v = 0; v < 16; ++v) {
+              float p0 = acc[0][v], p1 = acc[TI - 1][v];
+              swap_halves(p0, p1);
+              acc[0][v] = p0;
+              acc[TI - 1][v] = p1;
+            }
+          }
+          int sc = 0;   // FP8: the scale exponent of this lane's own values
+          if constexpr (PREC == P_FP8) sc = ew_own + evt;
+          float own = own_tau;
+          if constexpr (PREC == P_FP8) own = __builtin_ldexpf(own, -sc);
+#pragma unroll 1
+          for (int hh = 0; hh < (PAIR ? 2 : 1); ++hh) {
+            const int colh = PAIR ? hh : h;
+            float x[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const float y = (PAIR && hh) ? acc[TI - 1][v] : acc[0][v];
+              x[v] = fabsf(y);
+              if (masked) {
+                const int o = acc_row(v, colh);
+                if (o >= lim || o == myrow_own - j0) x[v] = -INFINITY;   // below every threshold
+              }
+            }
+            float gm[4];
+            int need = 0;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-              bool ok[4];
-              float x[4];
-              float gm = -1.0f;
+              gm[g] = fmaxf(fmaxf(x[4 * g], x[4 * g + 1]), fmaxf(x[4 * g + 2], x[4 * g + 3]));
+              need += gm[g] > own ? 4 : 0;
+            }
+            // every lane writes at index cnt + (its takes so far) in each group the
+            // wave enters: with cnt + need <= SW_Q - 1, or an empty queue and
+            // need <= 16 = SW_Q, no write leaves the lane's SW_Q entries
+            if (__ballot(cnt > 0 && cnt + need >= SW_Q)) {
+              flush();
+              own = own_tau;
+              if constexpr (PREC == P_FP8) own = __builtin_ldexpf(own, -sc);
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              if (!__ballot(gm[g] > own)) continue;
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
-                const int64_t j = j0 + acc_row(4 * g + e, h);
-                x[e] = fabsf(acc[t][4 * g + e]);
-                ok[e] = !masked || (j < a.n && j != myrow[t]);
-                gm = fmaxf(gm, ok[e] ? x[e] : -1.0f);
-              }
-              if (!__ballot(gm > thr[t])) continue;
-              if (__ballot(cnt[t] > SW_Q - 4)) {
-                flush();
-#pragma unroll
-                for (int t2 = 0; t2 < TI; ++t2) {
-                  thr[t2] = tau[t2];
-                  if constexpr (PREC == P_FP8) thr[t2] = __builtin_ldexpf(thr[t2], -(ewt[t2] + evt));
-                }
-              }
-              QEntry* qp = &queue[wave][owner(t)][PAIR ? h : 0][0];
-#pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const bool take = ok[e] && x[e] > thr[t];
-                float xv = x[e];
-                if constexpr (PREC == P_FP8) xv = __builtin_ldexpf(xv, ewt[t] + evt);
-                qp[cnt[t]] = QEntry{xv, (int)(j0 + acc_row(4 * g + e, h))};   // kept only if taken
-                cnt[t] += take ? 1 : 0;
+                const int v = 4 * g + e;
+                float xv = x[v];
+                const bool take = xv > own;
+                if constexpr (PREC == P_FP8) xv = __builtin_ldexpf(xv, sc);
+                // written unconditionally, kept only if taken
+                queue[wave][cnt][lane] = QEntry{xv, j0 + acc_row(v, colh)};
+                cnt += take ? 1 : 0;
               }
             }
           }
@@ -370,7 +409,7 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   const int to = PAIR ? h : 0;
   if (slot[to] >= 0) {
     const int sub = PAIR ? 0 : h;
-    const int64_t base = ((slot[to] * a.S + blockIdx.y) * NSUB + sub) * C;
+    const int64_t base = (((int64_t)slot[to] * a.S + blockIdx.y) * NSUB + sub) * C;
 #pragma unroll
     for (int s = 0; s < C; ++s) {
       a.cval[base + s] = lv[s];
