@@ -119,8 +119,8 @@ __device__ inline void swap_halves(int& x, int& y) {
 // one row tile each lane owns the list of its half row.
 __host__ __device__ constexpr bool sweep_pairs(int TI) { return TI == 2; }
 __host__ __device__ constexpr int sweep_nsub(int TI) { return sweep_pairs(TI) ? 1 : 2; }
-// V tiles per LDS stage: about 28 KB per stage buffer.
-__host__ __device__ constexpr int sweep_tps(int UNITS) { return 28 / UNITS > 0 ? 28 / UNITS : 1; }
+// V tiles per LDS stage: at most 44 KB per stage buffer (fewer barriers).
+__host__ __device__ constexpr int sweep_tps(int UNITS) { return 44 / UNITS > 0 ? 44 / UNITS : 1; }
 constexpr int SW_Q = 16;  // append-queue entries per lane (own list), in LDS
 static_assert(SW_Q >= 16, "the slow path appends up to 16 values per half row after a flush");
 
