@@ -138,7 +138,10 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   constexpr int TILE_U = UNITS * 64;              // chunks per V tile
   constexpr int STAGE_U = TPS * TILE_U;           // chunks per stage
   constexpr int PF = (STAGE_U + SW_THREADS - 1) / SW_THREADS;
-  __shared__ u32x4 lds[2][STAGE_U];
+  // two stage buffers as distinct objects: LDS reads of one are then known not
+  // to alias the global-to-LDS loads in flight into the other
+  __shared__ u32x4 lds_a[STAGE_U];
+  __shared__ u32x4 lds_b[STAGE_U];
   // queue[wave][entry][lane]: each lane appends to its own column
   __shared__ QEntry queue[SW_WAVES][SW_Q][64];
 
@@ -244,36 +247,25 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   const int jt1 = min(a.n_vtiles, jt0 + a.tiles_per_split);
   const int nst = jt1 > jt0 ? (jt1 - jt0 + TPS - 1) / TPS : 0;
 
-  u32x4 pf[PF];
-  auto load_stage = [&](int st) {
+  // Stage loads go straight from global memory into LDS (global_load_lds,
+  // 16 bytes per lane): lane l of a wave writes slot (its wave's base) + l, so
+  // chunk idx lands at lds[buf][idx].  Chunks past the column range are not
+  // loaded (their slots are never read).
+  auto load_stage = [&](int st, u32x4* dst) {
     const int64_t base = (int64_t)(jt0 + st * TPS) * TILE_U;
     const int64_t lim = (int64_t)jt1 * TILE_U;
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       const int idx = tid + q * SW_THREADS;
       const int64_t g = base + idx;
-      pf[q] = (idx < STAGE_U && g < lim) ? a.Vp[g] : u32x4{0, 0, 0, 0};
-    }
-  };
-  auto store_stage = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      const int idx = tid + q * SW_THREADS;
-      if (idx < STAGE_U) lds[buf][idx] = pf[q];
+      if (idx < STAGE_U && g < lim)
+        __builtin_amdgcn_global_load_lds((const void*)(a.Vp + g),
+                                         (__attribute__((address_space(3))) void*)(dst + (idx & ~63)), 16, 0, 0);
     }
   };
 
-  if (nst > 0) {
-    load_stage(0);
-    store_stage(0);
-  }
-  // All prologue loads (the B operands above all) have landed: without this
-  // the waitcnt analysis cannot prove it inside the loop and makes the MFMAs
-  // wait for the next stage's prefetch.
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    if (st + 1 < nst) load_stage(st + 1);        // global loads in flight during the MFMAs
+  // the MFMA sweep of stage st, whose V tiles are in rd
+  auto sweep_stage = [&](int st, const u32x4* rd) {
     if (active) {
 #pragma unroll 1
       for (int tt = 0; tt < TPS; ++tt) {
@@ -281,7 +273,7 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
         if (jt >= jt1) break;
         u32x4 av[UNITS];
 #pragma unroll
-        for (int u = 0; u < UNITS; ++u) av[u] = lds[st & 1][tt * TILE_U + u * 64 + lane];
+        for (int u = 0; u < UNITS; ++u) av[u] = rd[tt * TILE_U + u * 64 + lane];
         v16f acc[TI];
 #pragma unroll
         for (int t = 0; t < TI; ++t)
@@ -307,6 +299,8 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
         } else {
           masked = masked || (jt >= tile0 && jt < tile0 + TI);
         }
+        // wave-uniform by construction; say so, so that it stays a scalar branch
+        masked = __builtin_amdgcn_readfirstlane(masked ? 1 : 0) != 0;
         const int lim = n32 - j0;                  // columns at offsets >= lim do not exist
         int evt = 0;
         if constexpr (PREC == P_FP8) evt = a.ev[jt];
@@ -358,12 +352,13 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
             const int colh = PAIR ? hh : h;
             float x[16];
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              const float y = (PAIR && hh) ? acc[TI - 1][v] : acc[0][v];
-              x[v] = fabsf(y);
-              if (masked) {
+            for (int v = 0; v < 16; ++v) x[v] = fabsf((PAIR && hh) ? acc[TI - 1][v] : acc[0][v]);
+            if (masked) {
+              const int d = myrow_own - j0;
+#pragma unroll
+              for (int v = 0; v < 16; ++v) {
                 const int o = acc_row(v, colh);
-                if (o >= lim || o == myrow_own - j0) x[v] = -INFINITY;   // below every threshold
+                x[v] = (o >= lim || o == d) ? -INFINITY : x[v];   // below every threshold
               }
             }
             float gm[4];
@@ -399,7 +394,23 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
         }
       }
     }
-    if (st + 1 < nst) store_stage((st + 1) & 1);
+  };
+
+  if (nst > 0) load_stage(0, lds_a);
+  // every prologue load (the B operands, stage 0) has landed
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  // stages alternate between the buffers; the other buffer was last read in the
+  // previous stage, which every wave has left at the barrier
+  for (int st = 0; st < nst; st += 2) {
+    if (st + 1 < nst) load_stage(st + 1, lds_b);  // lands in LDS during the MFMAs
+    sweep_stage(st, lds_a);
+    __builtin_amdgcn_s_waitcnt(0);                // this wave's loads have landed
+    __syncthreads();                              // and everyone's
+    if (st + 1 >= nst) break;
+    if (st + 2 < nst) load_stage(st + 2, lds_a);
+    sweep_stage(st + 1, lds_b);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
