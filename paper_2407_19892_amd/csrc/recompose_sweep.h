@@ -147,7 +147,8 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  // the wave index is uniform within a wave: keep it (and all it derives) scalar
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int h = lane >> 5;
   const int l32 = lane & 31;
   const bool listed = a.row_list != nullptr;

@@ -4,9 +4,9 @@
 // (X = U S V^T with S^2 = e), so the n x n cell-axis Gram is never formed.
 //
 // A prep kernel folds the scale into an FP32 copy of the r leading
-// eigenvectors (p x 64W, row-major, zero padded), then one wave per CSR row
+// eigenvectors (p x rs, row-major, rs = W ceil(r / W), zero padded), then one wave per CSR row
 // gathers the rows of that panel named by the row's column indices and
-// accumulates in FP64: lane l owns output columns [W l, W l + W).  The
+// accumulates in FP64: lane l < rs / W owns output columns [W l, W l + W).  The
 // column/value pairs of a row are read once, 64 at a time, and broadcast
 // across the wave with lane reads.
 #include <hip/hip_runtime.h>
@@ -18,7 +18,7 @@
 
 namespace gmgm_sk {
 
-// Bp[g][j] = V[g + j ldv] / sqrt(e[j]) for j < r, 0 for r <= j < 64 W.
+// Bp[g][j] = V[g + j ldv] / sqrt(e[j]) for j < r, 0 for r <= j < rpad.
 __global__ void panel_kernel(const double* __restrict__ V, int64_t ldv, const double* __restrict__ e,
                              int64_t p, int r, int rpad, float* __restrict__ Bp, int* __restrict__ status) {
   const int64_t total = p * rpad;
@@ -78,7 +78,9 @@ __global__ void __launch_bounds__(256) spmm_kernel(const int64_t* __restrict__ r
   if (b < 0 || e < b || e > nnz) {
     if (lane == 0) atomicCAS(status, 0, DEV_BADINDEX);
   } else {
-    const T* Bl = reinterpret_cast<const T*>(Bp) + lane;
+    const int vl = (r + W - 1) / W;                 // vectors per panel row
+    const bool act = lane < vl;
+    const T* Bl = reinterpret_cast<const T*>(Bp) + (act ? lane : 0);
     for (int64_t t0 = b; t0 < e; t0 += 64) {
       const int64_t t = t0 + lane;
       int cc = 0;
@@ -102,7 +104,7 @@ __global__ void __launch_bounds__(256) spmm_kernel(const int64_t* __restrict__ r
         for (int u = 0; u < 8; ++u) {
           const int c = __builtin_amdgcn_readlane(cc, j + u);
           v[u] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), j + u));
-          bv[u] = Bl[(size_t)c * 64];   // a panel row holds 64 vectors of W floats
+          bv[u] = Bl[(size_t)c * vl];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) Vec<W>::add(acc, bv[u], (double)v[u]);
@@ -133,7 +135,7 @@ extern "C" gmgm_status gmgm_sketch(gmgm_ctx_t c, int64_t n, int64_t p, int64_t n
   GMGM_HIP(c, hipSetDevice(c->device));
   hipStream_t st = c->stream;
   const int W = r <= 64 ? 1 : r <= 128 ? 2 : 4;
-  const int rpad = 64 * W;
+  const int rpad = (int)((r + W - 1) / W * W);
   void* wB;
   GMGM_TRY(ws_get(c, WS_SKETCH, (size_t)p * rpad * sizeof(float), &wB));
   float* Bp = (float*)wB;
