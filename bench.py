@@ -40,7 +40,7 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
 # WRITE_SIZE runs scaled by the counters' readings on a 1 GiB copy (factors 2.0 and
 # 1.0); see profiles/recompose_bf16_1M_r100_k10_hbm_counters.md.  Keyed by the
 # kernel instantiation; set to None whenever that kernel changes.
-SWEEP_TRAFFIC_BYTES = {("bf16", 1_000_000, 100, 10): (10449818.9 * 2.0 + 250000.0) * 1024}
+SWEEP_TRAFFIC_BYTES = {}   # (prec, n, r, k) -> copy-calibrated FETCH_SIZE + WRITE_SIZE bytes of the current sweep
 
 
 def log(*a):
@@ -204,6 +204,28 @@ def shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, workers, p_pk=50_000, k_over=
     return res
 
 
+def library_gemm_tflops(dtype_name="bf16", n=16384, iters=10):
+    """Context for the roofline: the rate the vendor GEMM (torch.matmul ->
+    hipBLASLt) reaches on a large square product of the same dtype on this GPU,
+    i.e. the practically attainable share of the published MFMA peak."""
+    import torch
+    dt = {"bf16": torch.bfloat16, "fp32": torch.float32}[dtype_name]
+    a = torch.randn(n, n, device="cuda", dtype=dt)
+    b = torch.randn(n, n, device="cuda", dtype=dt)
+    for _ in range(3):
+        c = a @ b
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(iters):
+        c = a @ b
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / iters
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+
+
 def profile_run(g, Vd, pd, k, prec, n):
     """One metric step and one 1 GiB device copy (counter calibration)."""
     import torch
@@ -229,6 +251,7 @@ def main():
     ap.add_argument("--compare", default="fp32", help="precisions timed beside the metric")
     ap.add_argument("--compare-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gemm-reference", action="store_true", help="skip timing the library BF16 GEMM")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timings")
     ap.add_argument("--no-multimodal", action="store_true", help="skip the shared-cell-axis stage")
     ap.add_argument("--profile-run", action="store_true", help="one step + a 1 GiB copy, no JSON")
@@ -313,6 +336,11 @@ def main():
                         "stats": st, f"recall_of_{args.prec}_vs_{prec}": same / (n * k)}
         log(f"{prec}: {s * 1e3:.2f} ms/step, sweep {sw:.2f} ms, recall {same / (n * k):.6f}")
         del out
+    if args.prec == "bf16" and not args.no_gemm_reference:
+        lib = library_gemm_tflops("bf16")
+        result["roofline"]["library_gemm_tflops"] = lib
+        result["roofline"]["frac_of_library_gemm"] = result["roofline"]["achieved"] / lib
+        log(f"library BF16 GEMM 16384^3: {lib:.1f} TFLOP/s")
     if "fp32" in result:
         result["recall_vs_fp32"] = result["fp32"][f"recall_of_{args.prec}_vs_fp32"]
         result["speedup_vs_fp32"] = result["fp32"]["ms_per_step"] / result["ms_per_step"]

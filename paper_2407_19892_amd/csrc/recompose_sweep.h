@@ -228,11 +228,11 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
       }
     }
     cnt = 0;
-    // the k-th entry of the descending list: the minimum of its first k entries
-    // (a minimum rather than an index keeps the list in registers)
+    // the k-th entry of the descending list: the smallest of its first k entries
+    // (compare and select; an index would move the list out of registers)
     float kth = lv[0];
 #pragma unroll
-    for (int q = 1; q < C; ++q) kth = q < a.k ? fminf(kth, lv[q]) : kth;
+    for (int q = 1; q < C; ++q) kth = (q < a.k && lv[q] < kth) ? lv[q] : kth;
     own_tau = fmaxf(lv[C - 1], kth - beta2);
     if constexpr (PAIR) {
       float x = own_tau, y = own_tau;
@@ -335,6 +335,10 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
           // own-row values: with two row tiles, exchange the accumulators' lane
           // halves so that acc[0] / acc[1] hold columns acc_row(v, 0) / acc_row(v, 1)
           // of this lane's own row; with one tile, acc[0] holds half h of it
+          // the row maxima go through the same exchange: mh[c] is then the
+          // largest value of half c of the own row, and a half that no lane
+          // needs is skipped
+          float mh0 = m[0], mh1 = m[TI - 1];
           if constexpr (PAIR) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
@@ -343,13 +347,15 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
               acc[0][v] = p0;
               acc[TI - 1][v] = p1;
             }
+            swap_halves(mh0, mh1);
           }
           int sc = 0;   // FP8: the scale exponent of this lane's own values
           if constexpr (PREC == P_FP8) sc = ew_own + evt;
           float own = own_tau;
           if constexpr (PREC == P_FP8) own = __builtin_ldexpf(own, -sc);
-#pragma unroll 1
+#pragma unroll
           for (int hh = 0; hh < (PAIR ? 2 : 1); ++hh) {
+            if (PAIR && !__ballot((hh ? mh1 : mh0) > own)) continue;
             const int colh = PAIR ? hh : h;
             float x[16];
 #pragma unroll
