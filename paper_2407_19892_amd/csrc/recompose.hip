@@ -204,7 +204,7 @@ struct FinalArgs {
   float* val_out;
   int* fail_list;
   int* fail_count;
-  unsigned long long* counters;   // [0] candidates, [1] near ties (certified rows)
+  unsigned long long* counters;   // [0] candidates, [1] near ties (certified rows); null: not counted
 };
 
 constexpr int MAXK = 32;
@@ -298,18 +298,35 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
     }
     const unsigned long long mask = __ballot(take);
     const int pos = rc + __popcll(mask & ((1ull << lane) - 1ull));
-    if (take && pos < RCAP) {
-      const float* vj = a.V + (int64_t)j * a.r;
-      double s = 0.0;
-      for (int kk = 0; kk < a.r; ++kk) s = fma(wrow[wave][kk], (double)vj[kk], s);
-      rv[wave][pos] = s;
-      rj[wave][pos] = j;
-    }
+    if (take && pos < RCAP) rj[wave][pos] = j;
     rc += __popcll(mask);
   }
   __builtin_amdgcn_wave_barrier();
   const bool overflow = rc > RCAP;
   const int nr = rc < RCAP ? rc : RCAP;
+  // exact values, eight candidates at a time: lane group g (8 lanes) takes
+  // candidate c + g, its lane t the elements t, t + 8, ... (r <= 128), so that
+  // all of a group's loads are in flight together; fixed-order sum per group
+  {
+    const int g = lane >> 3, t = lane & 7;
+    for (int c = 0; c < nr; c += 8) {
+      const int q = c + g;
+      double s = 0.0;
+      if (q < nr) {
+        const float* vj = a.V + (int64_t)rj[wave][q] * a.r;
+        float x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x[u] = t + 8 * u < a.r ? vj[t + 8 * u] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (t + 8 * u < a.r) s = fma(wrow[wave][t + 8 * u], (double)x[u], s);
+      }
+#pragma unroll
+      for (int o = 4; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if (t == 0 && q < nr) rv[wave][q] = s;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
 
   // exact top-(k + 1) of R by (|value| desc, j asc)
   double pv = __builtin_inf();
@@ -355,8 +372,10 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
     if (mout >= 0.0) ok = mout + beta < tk;
   }
   if (lane == 0) {
-    atomicAdd(&a.counters[0], (unsigned long long)nvalid);
-    if (ok && nsel > a.k && tk - fabs(sel_v[wave][a.k]) <= 1e-6 * tk) atomicAdd(&a.counters[1], 1ull);
+    if (a.counters) {   // statistics requested
+      atomicAdd(&a.counters[0], (unsigned long long)nvalid);
+      if (ok && nsel > a.k && tk - fabs(sel_v[wave][a.k]) <= 1e-6 * tk) atomicAdd(&a.counters[1], 1ull);
+    }
     if (!ok) {
       const int pos = atomicAdd(a.fail_count, 1);
       a.fail_list[pos] = (int)i;
@@ -697,7 +716,7 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
   fa.val_out = val_out;
   fa.fail_list = list1;
   fa.fail_count = cnt1;
-  fa.counters = counters;
+  fa.counters = stats ? counters : nullptr;   // counted only when asked for
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, st, fa);
   hipLaunchKernelGGL(row_ptr_kernel, dim3((unsigned)ceil_div(rows + 1, 256)), dim3(256), 0, st,
                      row_ptr_out, rows, k);
@@ -759,7 +778,7 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
     fb.cprec = cprec_for(P_F32, kpadB);
     fb.fail_list = list2;
     fb.fail_count = cnt2;
-    fb.counters = counters + 2;    // stage-B candidates are not counted with stage A's
+    fb.counters = stats ? counters + 2 : nullptr;   // stage-B candidates are not counted with stage A's
     hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)ceil_div(h1, 4)), dim3(256), 0, st, fb);
     GMGM_HIP(c, hipGetLastError());
     flops += 2.0 * (double)wtB * 32.0 * n_vtiles * 32.0 * kpadB;
