@@ -40,7 +40,7 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
 # WRITE_SIZE runs scaled by the counters' readings on a 1 GiB copy (factors 2.0 and
 # 1.0); see profiles/recompose_bf16_1M_r100_k10_hbm_counters.md.  Keyed by the
 # kernel instantiation; set to None whenever that kernel changes.
-SWEEP_TRAFFIC_BYTES = {}   # (prec, n, r, k) -> copy-calibrated FETCH_SIZE + WRITE_SIZE bytes of the current sweep
+SWEEP_TRAFFIC_BYTES = {("bf16", 1_000_000, 100, 10): (8833160.3 * 2.0 + 250000.0) * 1024}
 
 
 def log(*a):
