@@ -9,8 +9,9 @@ Everything here is plain NumPy in float64, written from the paper (arXiv
 partial eigendecomposition and the cell-axis factor (Algorithm 1, Theorem 1),
 the eigenvalue maximum-likelihood estimate (model equation, eigenvalue-gradient
 Proposition, Existence lemma), the eigen-recomposition with per-row top-k
-thresholding (Algorithm 1's final loop and the complexity appendix), and the
-learned warm start's multilayer perceptron.
+thresholding (Algorithm 1's final loop and the complexity appendix), the
+significance threshold of Theorem 3 and the thresholded graph it defines, and
+the learned warm start's multilayer perceptron.
 
 Readings of passages that are silent or ambiguous are stated in the docstring
 of the function that takes them.
@@ -22,10 +23,11 @@ from .recompose import psi_dense, psi_rows, psi_blockwise
 from .topk import topk_row, topk_csr, near_tie_rows
 from . import warmstart
 from . import range_finder
+from . import significance
 
 __all__ = [
     "gram_dense", "gram_csr", "eigh_desc", "numerical_rank", "cell_factor",
     "Problem", "nll", "grad", "solve_eigs", "alg1_gradient_descent", "default_eps",
     "psi_dense", "psi_rows", "psi_blockwise", "topk_row", "topk_csr", "near_tie_rows",
-    "warmstart", "range_finder",
+    "warmstart", "range_finder", "significance",
 ]
