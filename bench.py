@@ -204,6 +204,39 @@ def shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, workers, p_pk=50_000, k_over=
     return res
 
 
+def threshold_leg(g, Vd, pd, topk_out, k, prec, n, r, steps=5, warmup=2):
+    """The fixed-threshold form of the same recomposition (Theorem 3's
+    significance rule uses it): rows/s at the threshold that keeps about k
+    entries per row, taken as the median over rows of the k-th largest |Psi|
+    from the top-k output."""
+    import torch
+    kth = topk_out[2].view(n, k).abs().min(dim=1).values
+    thr = float(kth.median().item())
+    res = g.recompose_threshold(Vd, pd, thr, prec=prec)      # sizes the output
+    cap = res.nnz
+    for _ in range(warmup):
+        res = g.recompose_threshold(Vd, pd, thr, prec=prec, capacity=cap)
+    g.sync()
+    g.kernel_times()
+    g.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = g.recompose_threshold(Vd, pd, thr, prec=prec, capacity=cap)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    g.set_timing(False)
+    sweep_ms, cnt = g.kernel_times()
+    sweep_ms /= steps            # both sweeps of a call (all rows, then the rows with many candidates)
+    flops = 2.0 * r * n * n
+    log(f"threshold {thr:.4g}: {dt * 1e3:.2f} ms/step, sweep {sweep_ms:.2f} ms, nnz {res.nnz}")
+    return {"thr": thr, "rule": "median over rows of the k-th largest |Psi| (about k kept per row)",
+            "rows_per_s": n / dt, "ms_per_step": dt * 1e3, "sweep_ms": sweep_ms,
+            "sweep_tflops": flops / (sweep_ms * 1e-3) / 1e12,
+            "sweep_frac_of_peak": flops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], "nnz": res.nnz,
+            "sweep_launches_per_call": cnt / steps}
+
+
 def library_gemm_tflops(dtype_name="bf16", n=16384, iters=10):
     """Context for the roofline: the rate the vendor GEMM (torch.matmul ->
     hipBLASLt) reaches on a large square product of the same dtype on this GPU,
@@ -252,6 +285,7 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gemm-reference", action="store_true", help="skip timing the library BF16 GEMM")
+    ap.add_argument("--no-threshold", action="store_true", help="skip the fixed-threshold recomposition")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timings")
     ap.add_argument("--no-multimodal", action="store_true", help="skip the shared-cell-axis stage")
     ap.add_argument("--profile-run", action="store_true", help="one step + a 1 GiB copy, no JSON")
@@ -336,6 +370,8 @@ def main():
                         "stats": st, f"recall_of_{args.prec}_vs_{prec}": same / (n * k)}
         log(f"{prec}: {s * 1e3:.2f} ms/step, sweep {sw:.2f} ms, recall {same / (n * k):.6f}")
         del out
+    if not args.no_threshold:
+        result["threshold"] = threshold_leg(g, Vd, pd, out_main, k, args.prec, n, r)
     if args.prec == "bf16" and not args.no_gemm_reference:
         lib = library_gemm_tflops("bf16")
         result["roofline"]["library_gemm_tflops"] = lib

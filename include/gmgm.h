@@ -128,6 +128,63 @@ gmgm_status gmgm_recompose_topk(gmgm_ctx_t ctx, int64_t n, int64_t r, const floa
                                 gmgm_topk_stats* stats);
 
 /*
+ * Fused eigen-recomposition with a fixed threshold into CSR: the significance
+ * rule of Theorem 3 (keep the statistically significant edges), or any fixed
+ * threshold.  For each row i in [row_begin, row_end) of Psi = V diag(psi) V^T,
+ *   keep every column j != i with |Psi_ij| >= thr, in ascending j,
+ * without forming Psi.
+ *
+ *   n, r, V, psi, row_begin, row_end, prec   as gmgm_recompose_topk.
+ *   thr         the threshold, positive and finite (GMGM_E_DOMAIN otherwise).
+ *   max_per_row > 0: a row keeping more entries is an error (GMGM_E_OVERFLOW);
+ *               <= 0: no limit.
+ *   row_ptr_out (row_end - row_begin + 1) int64 (device), always written.
+ *   col_out, val_out   `capacity` int32 / FP32 entries (device); Psi_ij
+ *               (signed) rounded from the FP64 value.
+ *   capacity    room in col_out / val_out (>= 0); the call also uses this
+ *               many entries of workspace.
+ *   nnz_out     host int64: the number of kept entries.
+ * The MFMA sweep in `prec` keeps every value within the row's rounding bound
+ * of the threshold (up to 1024 per row); these candidates are decided exactly
+ * in FP64, and rows with more candidates are scanned exactly, so the output
+ * does not depend on `prec`.  When the total exceeds `capacity` the call
+ * returns GMGM_E_OVERFLOW with *nnz_out and row_ptr_out holding the true
+ * sizes, so that the caller can size the output and call again.
+ * GMGM_E_DOMAIN for non-finite V or psi.  Synchronises.
+ */
+gmgm_status gmgm_recompose_threshold(gmgm_ctx_t ctx, int64_t n, int64_t r, const float* V,
+                                     const double* psi, int64_t row_begin, int64_t row_end,
+                                     double thr, gmgm_prec prec, int32_t max_per_row,
+                                     int64_t* row_ptr_out, int32_t* col_out, float* val_out,
+                                     int64_t capacity, int64_t* nnz_out);
+
+/*
+ * The significance threshold of Theorem 3 for axis l (host computation).
+ * Under the null hypothesis that modality gamma has precision sigma_gamma^-2 I,
+ * an edge psi_lij is asymptotically N(0, 4 d_l / sum_gamma d^gamma_all
+ * sigma_gamma^4), the sum over the n_mod modalities that contain axis l; the
+ * two-sided Bonferroni test at level alpha over n_tests edges keeps
+ *   |psi_lij| >= 2 z sqrt(d_l / sum_gamma d^gamma_all sigma_gamma^4),
+ *   z = Phi^-1(1 - alpha / (2 n_tests)).
+ *
+ *   d_l         size of axis l (>= 2).
+ *   n_mod       number of modalities containing axis l (>= 1).
+ *   d_all       n_mod host doubles: d^gamma_all, the product of the modality's
+ *               axis sizes.
+ *   trace_s     n_mod host doubles: tr(S^gamma), the modality's sum of squared
+ *               entries; sigma_gamma^2 = trace_s / d_all (the null model's
+ *               maximum-likelihood variance).
+ *   alpha       test level in (0, 1).
+ *   n_tests     Bonferroni count; <= 0 selects d_l (d_l - 1) / 2.
+ *   thr_out     host double.
+ * No device work; ctx may be NULL (errors are then returned without a
+ * message).
+ */
+gmgm_status gmgm_significance_threshold(gmgm_ctx_t ctx, int64_t d_l, int32_t n_mod, const double* d_all,
+                                        const double* trace_s, double alpha, double n_tests,
+                                        double* thr_out);
+
+/*
  * Small-axis Gram matrix G = X^T X (problem setup: S_l = mat_l[D] mat_l[D]^T,
  * formed only for the small axis; no centring or scaling).
  *

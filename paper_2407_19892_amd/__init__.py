@@ -62,6 +62,11 @@ SIGNATURES = {
     "gmgm_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "gmgm_recompose_topk": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, _I64, _I32, ctypes.c_int,
                                            _I32, _P, _P, _P, ctypes.POINTER(TopkStats)]),
+    "gmgm_recompose_threshold": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, _I64, ctypes.c_double, ctypes.c_int,
+                                                _I32, _P, _P, _P, _I64, ctypes.POINTER(_I64)]),
+    "gmgm_significance_threshold": (ctypes.c_int, [_P, _I64, _I32, ctypes.POINTER(ctypes.c_double),
+                                                   ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                                   ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "gmgm_gram": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
     "gmgm_eigh_small": (ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.POINTER(_I64)]),
     "gmgm_sketch": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _I64, _P, _I64, _P]),
@@ -193,6 +198,67 @@ def recompose_topk(V, psi, k: int, prec: str = "bf16", row_begin: int = 0, row_e
               "rows_near_tie": st.rows_near_tie, "rows_exact": st.rows_exact,
               "mfma_flops": st.mfma_flops}
     return TopkResult(rp, col, val, sd)
+
+
+@dataclass
+class ThresholdResult:
+    row_ptr: "object"
+    col: "object"
+    val: "object"
+    nnz: int
+
+
+def recompose_threshold(V, psi, thr: float, prec: str = "bf16", row_begin: int = 0, row_end: int | None = None,
+                        max_per_row: int = 0, capacity: int | None = None) -> ThresholdResult:
+    """CSR of every |Psi_ij| >= thr, j != i, of Psi = V diag(psi) V^T (see
+    gmgm_recompose_threshold).  The output arrays first get `capacity` entries
+    (default 16 per row); when the library reports more, they are resized to
+    the reported count and the call is repeated once."""
+    import torch
+    if not (V.is_cuda and psi.is_cuda):
+        raise ValueError("V and psi must be device tensors")
+    if V.dtype != torch.float32 or psi.dtype != torch.float64:
+        raise TypeError("V must be float32 and psi float64")
+    if not V.is_contiguous() or not psi.is_contiguous() or V.dim() != 2:
+        raise ValueError("V must be a contiguous 2-D tensor and psi contiguous")
+    n, r = V.shape
+    if psi.numel() != r:
+        raise ValueError("psi must have r entries")
+    row_end = n if row_end is None else row_end
+    rows = max(0, row_end - row_begin)
+    cap = rows * 16 if capacity is None else capacity
+    c = context(V.device.index)
+    rp = torch.empty(rows + 1, dtype=torch.int64, device=V.device)
+    for attempt in range(2):
+        col = torch.empty(max(cap, 1), dtype=torch.int32, device=V.device)
+        val = torch.empty(max(cap, 1), dtype=torch.float32, device=V.device)
+        nnz = _I64(0)
+        st = load().gmgm_recompose_threshold(c, n, r, _ptr(V), _ptr(psi), row_begin, row_end, float(thr),
+                                              PREC[prec], max_per_row, _ptr(rp), _ptr(col), _ptr(val), cap,
+                                              ctypes.byref(nnz))
+        if st == 5 and attempt == 0 and nnz.value > cap and "capacity" in load().gmgm_last_error(c).decode():
+            cap = nnz.value
+            continue
+        _check(c, st)
+        break
+    return ThresholdResult(rp, col[:nnz.value], val[:nnz.value], nnz.value)
+
+
+def significance_threshold(d_l: int, d_all, trace_s, alpha: float = 0.05, n_tests: float = 0.0) -> float:
+    """Theorem 3's threshold for axis l (see gmgm_significance_threshold; host
+    arithmetic, no device needed)."""
+    d_all = [float(x) for x in d_all]
+    trace_s = [float(x) for x in trace_s]
+    if len(d_all) != len(trace_s):
+        raise ValueError("d_all and trace_s must have one entry per modality")
+    m = len(d_all)
+    arr = ctypes.c_double * m
+    out = ctypes.c_double(0.0)
+    st = load().gmgm_significance_threshold(None, int(d_l), m, arr(*d_all), arr(*trace_s), float(alpha),
+                                            float(n_tests), ctypes.byref(out))
+    if st != 0:
+        raise GmgmError(st, "gmgm_significance_threshold rejected its arguments")
+    return out.value
 
 
 @dataclass

@@ -578,6 +578,244 @@ static void launch_repack(int prec, F&& f) {
   else f(repack_kernel<P_FP8>);
 }
 
+
+// ---------------------------------------------------------------------------
+// Threshold mode: every j != i with |Psi_ij| >= thr (the significance
+// threshold of Theorem 3, or any fixed threshold), as CSR.
+
+constexpr int THR_CAPT = 1024;   // sweep candidates per row (more: exact scan)
+
+struct ThrArgs {
+  const float* V;
+  const double* psi;
+  int64_t n;
+  int r;
+  double thr;
+  int64_t row_begin, rows;
+  const int* cidx;          // candidates, ascending j per row: [slot][THR_CAPT], or at toff[q]
+  const int* tcount;        // per verified row; above its room: overflowed
+  const int* list;          // verified rows (slots), or null: every slot in order
+  const long long* toff;    // with list: candidate offsets per listed row (room: the next offset)
+  int* fail_rows;           // overflowed rows as global row ids (for a listed re-sweep)
+  int* pool_j;              // kept entries, one contiguous run per row
+  float* pool_v;
+  long long pool_cap;
+  long long* pool_top;      // bump allocator (may pass pool_cap: then nothing is written)
+  long long* pool_off;      // [slot]
+  int* kept_n;              // [slot]
+  int* fail_list;           // rows whose candidates overflowed (exact scan)
+  int* fail_count;
+};
+
+// One wave per row: exact FP64 value of every candidate (eight-lane groups, as
+// in finalize), kept when |Psi_ij| >= thr; the candidates arrive in ascending
+// j, and the kept ones are written in that order to a run reserved in the pool.
+__global__ void __launch_bounds__(256) thr_verify_kernel(ThrArgs a) {
+  __shared__ double wrow[4][128];
+  __shared__ double sv[4][THR_CAPT];    // exact values of the candidates, chunk by chunk
+  __shared__ long long soff[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t qv = (int64_t)blockIdx.x * 4 + wave;      // index among the verified rows
+  if (qv >= a.rows) return;
+  const int64_t slot = a.list ? a.list[qv] : qv;
+  const int64_t i = a.row_begin + slot;
+  const int m = a.tcount[qv];
+  const int room = a.list ? (int)(a.toff[qv + 1] - a.toff[qv]) : THR_CAPT;
+  if (m > room) {
+    if (lane == 0) {
+      const int f = atomicAdd(a.fail_count, 1);
+      a.fail_list[f] = (int)slot;
+      if (a.fail_rows) a.fail_rows[f] = (int)i;
+    }
+    return;
+  }
+  for (int q = lane; q < a.r; q += 64) wrow[wave][q] = (double)a.V[i * a.r + q] * a.psi[q];
+  __builtin_amdgcn_wave_barrier();
+  const int* cj = a.cidx + (a.list ? a.toff[qv] : slot * THR_CAPT);
+  const int g = lane >> 3, t = lane & 7;
+  // the exact value of candidate q (lanes of group g = q % 8 take part; the sum
+  // lands on every lane of the group)
+  auto exact = [&](int q) {
+    double s = 0.0;
+    if (q < m) {
+      const float* vj = a.V + (int64_t)cj[q] * a.r;
+      float x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = t + 8 * u < a.r ? vj[t + 8 * u] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (t + 8 * u < a.r) s = fma(wrow[wave][t + 8 * u], (double)x[u], s);
+    }
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+  };
+  // pass 1: count the kept candidates (caching their values when they fit)
+  const bool cached = m <= THR_CAPT;
+  int kept = 0;
+  for (int c = 0; c < m; c += 8) {
+    const int q = c + g;
+    const double s = exact(q);
+    const bool keep = t == 0 && q < m && cj[q] != (int)i && fabs(s) >= a.thr;
+    if (cached && t == 0 && q < m) sv[wave][q] = keep ? s : __builtin_nan("");
+    kept += __popcll(__ballot(keep));
+  }
+  if (lane == 0) {
+    soff[wave] = atomicAdd((unsigned long long*)a.pool_top, (unsigned long long)kept);
+    a.pool_off[slot] = soff[wave];
+    a.kept_n[slot] = kept;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const long long off = soff[wave];
+  if (off + kept > a.pool_cap) return;       // the pool is too small: sizes only
+  // pass 2: the kept candidates, in order, into the row's run
+  int pos = 0;
+  if (cached) {
+    for (int c = 0; c < m; c += 64) {
+      const int q = c + lane;
+      const bool keep = q < m && !(sv[wave][q] != sv[wave][q]);
+      const unsigned long long mask = __ballot(keep);
+      if (keep) {
+        const long long o = off + pos + __popcll(mask & ((1ull << lane) - 1ull));
+        a.pool_j[o] = cj[q];
+        a.pool_v[o] = (float)sv[wave][q];
+      }
+      pos += __popcll(mask);
+    }
+  } else {
+    for (int c = 0; c < m; c += 8) {
+      const int q = c + g;
+      const double s = exact(q);
+      const bool keep = t == 0 && q < m && cj[q] != (int)i && fabs(s) >= a.thr;
+      const unsigned long long mask = __ballot(keep);
+      if (keep) {
+        const long long o = off + pos + __popcll(mask & ((1ull << lane) - 1ull));
+        a.pool_j[o] = cj[q];
+        a.pool_v[o] = (float)s;
+      }
+      pos += __popcll(mask);
+    }
+  }
+}
+
+// Rows whose candidates overflowed: one workgroup per row scans every column
+// exactly in FP64 twice, to count and then to write its run in column order.
+__global__ void __launch_bounds__(256) thr_exact_kernel(ThrArgs a) {
+  __shared__ double wrow[128];
+  __shared__ int wcnt[4];
+  __shared__ long long soff;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cnt = *a.fail_count;
+  for (int f = blockIdx.x; f < cnt; f += gridDim.x) {
+    const int64_t slot = a.fail_list[f];
+    const int64_t i = a.row_begin + slot;
+    __syncthreads();
+    for (int q = tid; q < a.r; q += 256) wrow[q] = (double)a.V[i * a.r + q] * a.psi[q];
+    __syncthreads();
+    long long off = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      long long kept = 0;   // uniform across the workgroup
+      for (int64_t j0 = 0; j0 < a.n; j0 += 256) {
+        const int64_t j = j0 + tid;
+        bool keep = false;
+        double s = 0.0;
+        if (j < a.n && j != i) {
+          const float* vj = a.V + j * a.r;
+          for (int kk = 0; kk < a.r; ++kk) s = fma(wrow[kk], (double)vj[kk], s);
+          keep = fabs(s) >= a.thr;
+        }
+        const unsigned long long mask = __ballot(keep);
+        if (lane == 0) wcnt[wave] = __popcll(mask);
+        __syncthreads();
+        long long before = kept;
+        for (int w = 0; w < wave; ++w) before += wcnt[w];
+        const long long o = off + before + __popcll(mask & ((1ull << lane) - 1ull));
+        if (pass == 1 && keep && o < a.pool_cap) {
+          a.pool_j[o] = (int)j;
+          a.pool_v[o] = (float)s;
+        }
+        kept += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        __syncthreads();
+      }
+      if (pass == 0) {
+        if (tid == 0) {
+          soff = atomicAdd((unsigned long long*)a.pool_top, (unsigned long long)kept);
+          a.pool_off[slot] = soff;
+          a.kept_n[slot] = (int)kept;
+        }
+        __syncthreads();
+        off = soff;
+        if (off + kept > a.pool_cap) break;   // sizes only
+      }
+    }
+  }
+}
+
+// Candidate counts of the listed rows (out[q] = count[list[q]]).
+__global__ void thr_counts_kernel(const int* __restrict__ list, int nl, const int* __restrict__ count,
+                                  int* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nl) out[q] = count[list[q]];
+}
+
+// One workgroup: row_ptr = exclusive prefix sum of the kept counts (int64),
+// plus the total and the largest count (info[0], info[1]).
+__global__ void __launch_bounds__(1024) thr_scan_kernel(const int* __restrict__ kept_n, int64_t rows,
+                                                        int64_t* __restrict__ row_ptr,
+                                                        long long* __restrict__ info) {
+  __shared__ long long part[1024];
+  __shared__ int pmax[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (rows + 1023) / 1024;
+  const int64_t b = tid * per, e = min(rows, b + per);
+  long long sum = 0;
+  int mx = 0;
+  for (int64_t q = b; q < e; ++q) {
+    sum += kept_n[q];
+    mx = max(mx, kept_n[q]);
+  }
+  part[tid] = sum;
+  pmax[tid] = mx;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan (Hillis-Steele)
+    const long long v = tid >= off ? part[tid - off] : 0;
+    const int m2 = tid >= off ? pmax[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    pmax[tid] = max(pmax[tid], m2);
+    __syncthreads();
+  }
+  long long run = tid > 0 ? part[tid - 1] : 0;
+  for (int64_t q = b; q < e; ++q) {
+    row_ptr[q] = run;
+    run += kept_n[q];
+  }
+  if (tid == 1023) {
+    row_ptr[rows] = part[1023];
+    info[0] = part[1023];
+    info[1] = pmax[1023];
+  }
+}
+
+// One wave per row: its run of the pool into the CSR arrays.
+__global__ void __launch_bounds__(256) thr_gather_kernel(const int* __restrict__ pool_j, const float* __restrict__ pool_v,
+                                                         const long long* __restrict__ pool_off,
+                                                         const int* __restrict__ kept_n, const int64_t* __restrict__ row_ptr,
+                                                         int64_t rows, int32_t* __restrict__ col_out,
+                                                         float* __restrict__ val_out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (slot >= rows) return;
+  const int64_t o = row_ptr[slot];
+  const long long src = pool_off[slot];
+  const int cnt = kept_n[slot];
+  for (int q = lane; q < cnt; q += 64) {
+    col_out[o + q] = pool_j[src + q];
+    val_out[o + q] = pool_v[src + q];
+  }
+}
+
 }  // namespace gmgm_rc
 
 using namespace gmgm_rc;
@@ -802,4 +1040,276 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
     stats->mfma_flops = flops;
   }
   return GMGM_OK;
+}
+
+extern "C" gmgm_status gmgm_recompose_threshold(gmgm_ctx_t c, int64_t n, int64_t r, const float* V,
+                                                const double* psi, int64_t row_begin, int64_t row_end,
+                                                double thr, gmgm_prec prec_e, int32_t max_per_row,
+                                                int64_t* row_ptr_out, int32_t* col_out, float* val_out,
+                                                int64_t capacity, int64_t* nnz_out) {
+  GMGM_CHECK_CTX(c);
+  const int prec = (int)prec_e;
+  if (prec < 0 || prec > 2) return set_err(c, GMGM_E_ARG, "unknown precision %d", prec);
+  if (n < 2 || n > 0x7fffffc0LL) return set_err(c, GMGM_E_SHAPE, "n = %lld out of range [2, 2^31 - 64]", (long long)n);
+  if (r < 1 || r > 128) return set_err(c, GMGM_E_SHAPE, "r = %lld must be in [1, 128]", (long long)r);
+  if (row_begin < 0 || row_end > n || row_begin >= row_end)
+    return set_err(c, GMGM_E_SHAPE, "row range [%lld, %lld) invalid for n = %lld",
+                   (long long)row_begin, (long long)row_end, (long long)n);
+  if (!(thr > 0.0) || !std::isfinite(thr)) return set_err(c, GMGM_E_DOMAIN, "thr must be positive and finite");
+  if (capacity < 0 || !V || !psi || !row_ptr_out || !nnz_out || (capacity > 0 && (!col_out || !val_out)))
+    return set_err(c, GMGM_E_ARG, "null pointer or negative capacity");
+  GMGM_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+
+  const int kpad = kpad_for(prec, (int)r);
+  SweepFn sweep = pick_sweep_thr(prec, kpad);
+  if (!sweep) return set_err(c, GMGM_E_SHAPE, "no sweep variant for r = %lld", (long long)r);
+  const int TI = 2;                       // pair mode: one whole row per lane
+  const int units = kpad / chunk_elems(prec) / 2;
+  const int64_t rows = row_end - row_begin;
+  const int n_vtiles = (int)ceil_div(n, 32);
+  const int rt_begin = (int)(row_begin / 32);
+  const int n_wtiles = (int)ceil_div(row_end, 32) - rt_begin;
+  const int64_t w_lo = (int64_t)rt_begin * 32;
+  const int64_t w_rows = (int64_t)n_wtiles * 32;
+  const int64_t gx = ceil_div(n_wtiles, (int64_t)SW_WAVES * TI);
+  // one column split, so that each row's candidates come out in column order
+  const int S = 1;
+  const long long pool_cap = std::max<long long>(capacity, 1);
+
+  void *vp, *norms, *misc, *scl, *pool, *aux;
+  GMGM_TRY(ws_get(c, WS_VP, (size_t)n_vtiles * units * 64 * 16, &vp));
+  GMGM_TRY(ws_get(c, WS_NORMS, (size_t)n * 4 + (size_t)w_rows * 12 + 256, &norms));
+  GMGM_TRY(ws_get(c, WS_MISC, 256, &misc));
+  GMGM_TRY(ws_get(c, WS_SCALES, ((size_t)n_vtiles + (size_t)w_rows) * 4 + 64, &scl));
+  GMGM_TRY(ws_get(c, WS_THR0, (size_t)pool_cap * 8, &pool));
+  GMGM_TRY(ws_get(c, WS_THR1, (size_t)rows * 24 + 64, &aux));
+  StageBufs A;
+  GMGM_TRY(stage_buffers(c, WS_WP, WS_CAND, n_wtiles, units, rows, S, 1, THR_CAPT, &A));
+  A.vp = (const u32x4*)vp;
+  float* vrowmax = (float*)norms;
+  double* wnorm = (double*)((char*)norms + (((size_t)n * 4 + 15) & ~(size_t)15));
+  float* wrowmax = (float*)(wnorm + w_rows);
+  unsigned* vmax_bits = (unsigned*)misc;
+  int* fail_count = (int*)((char*)misc + 16);
+  long long* pool_top = (long long*)((char*)misc + 32);
+  long long* info = (long long*)((char*)misc + 64);
+  int* ev = (int*)scl;
+  int* ew = ev + n_vtiles;
+  long long* pool_off = (long long*)aux;
+  int* tcount = (int*)(pool_off + rows);
+  int* kept_n = tcount + rows;
+  int* fail_list = kept_n + rows;
+  int* fail_rows = fail_list + rows;
+  int* fail_count2 = (int*)((char*)misc + 20);
+  int* pool_j = (int*)pool;
+  float* pool_v = (float*)((char*)pool + (size_t)pool_cap * 4);
+
+  GMGM_HIP(c, hipMemsetAsync(misc, 0, 128, st));
+  const int prep_blocks = (int)std::min<int64_t>(ceil_div(n, 4), 4096);
+  hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, st, V, psi, n, (int)r, w_lo,
+                     std::min<int64_t>(n, w_lo + w_rows), vrowmax, wnorm, wrowmax, vmax_bits,
+                     c->dev_status);
+  if (prec == P_FP8) {
+    const int64_t m = std::max<int64_t>(n_vtiles, w_rows);
+    hipLaunchKernelGGL(fp8_exps_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, vrowmax,
+                       n, n_vtiles, wrowmax, w_rows, ev, ew);
+  }
+  const int nch = kpad / chunk_elems(prec);
+  launch_repack(prec, [&](auto kern) {
+    const int64_t tv = (int64_t)n_vtiles * 32 * nch, tw = w_rows * nch;
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(tv, 256)), dim3(256), 0, st, V, psi, (int64_t)0,
+                       n, (int64_t)n_vtiles * 32, (int)r, kpad, false, ev, true, (const int*)nullptr,
+                       (const int*)nullptr, (u32x4*)vp);
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(tw, 256)), dim3(256), 0, st, V, psi, w_lo, n,
+                       w_rows, (int)r, kpad, true, ew, false, (const int*)nullptr,
+                       (const int*)nullptr, (u32x4*)A.wp);
+  });
+  SweepArgs sa{};
+  sa.Vp = A.vp;
+  sa.Wp = A.wp;
+  sa.ev = ev;
+  sa.ew = ew;
+  sa.cval = A.cval;
+  sa.cidx = A.cidx;
+  sa.n = n;
+  sa.n_vtiles = n_vtiles;
+  sa.n_wtiles = n_wtiles;
+  sa.row0 = w_lo;
+  sa.row_begin = row_begin;
+  sa.row_end = row_end;
+  sa.S = S;
+  sa.tiles_per_split = n_vtiles;
+  sa.wnorm = wnorm;
+  sa.vmax_bits = vmax_bits;
+  sa.w_lo = w_lo;
+  sa.cprec = cprec_for(prec, kpad);
+  sa.k = 1;
+  sa.thr = thr;
+  sa.capt = THR_CAPT;
+  sa.tcount = tcount;
+  hipEvent_t t0 = timing_start(c);
+  sweep<<<dim3((unsigned)gx, 1), dim3(SW_THREADS), 0, st>>>(sa);
+  timing_stop(c, t0);
+  GMGM_HIP(c, hipGetLastError());
+
+  ThrArgs ta{};
+  ta.V = V;
+  ta.psi = psi;
+  ta.n = n;
+  ta.r = (int)r;
+  ta.thr = thr;
+  ta.row_begin = row_begin;
+  ta.rows = rows;
+  ta.cidx = A.cidx;
+  ta.tcount = tcount;
+  ta.list = nullptr;
+  ta.toff = nullptr;
+  ta.fail_rows = fail_rows;
+  ta.pool_j = pool_j;
+  ta.pool_v = pool_v;
+  ta.pool_cap = capacity;
+  ta.pool_top = pool_top;
+  ta.pool_off = pool_off;
+  ta.kept_n = kept_n;
+  ta.fail_list = fail_list;
+  ta.fail_count = fail_count;
+  hipLaunchKernelGGL(thr_verify_kernel, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, st, ta);
+  int h_fail = 0;
+  GMGM_HIP(c, hipMemcpyAsync(&h_fail, fail_count, 4, hipMemcpyDeviceToHost, st));
+  GMGM_HIP(c, hipStreamSynchronize(st));
+  if (h_fail > 0) {
+    // ---- rows with more candidates than the sweep's room: re-swept as a
+    // list, with room for exactly the candidates the first sweep counted
+    // (BF16 operands when the first sweep used FP8, whose per-row scales are
+    // not kept for listed rows)
+    void* auxB;
+    GMGM_TRY(ws_get(c, WS_THR2, (size_t)h_fail * 12 + (size_t)(h_fail + 1) * 8 + 64, &auxB));
+    long long* toffB = (long long*)auxB;
+    int* cntB = (int*)(toffB + h_fail + 1);
+    int* tcountB = cntB + h_fail;
+    int* fail2 = tcountB + h_fail;
+    long long* infoB = info + 2;
+    hipLaunchKernelGGL(thr_counts_kernel, dim3((unsigned)ceil_div(h_fail, 256)), dim3(256), 0, st, fail_list,
+                       h_fail, tcount, cntB);
+    hipLaunchKernelGGL(thr_scan_kernel, dim3(1), dim3(1024), 0, st, cntB, (int64_t)h_fail, (int64_t*)toffB, infoB);
+    long long totB = 0;
+    GMGM_HIP(c, hipMemcpyAsync(&totB, infoB, 8, hipMemcpyDeviceToHost, st));
+    GMGM_HIP(c, hipStreamSynchronize(st));
+    const int precB = prec == P_F32 ? P_F32 : P_BF16;
+    const int kpadB = kpad_for(precB, (int)r);
+    const int unitsB = kpadB / chunk_elems(precB) / 2;
+    SweepFn sweepB = pick_sweep_thr(precB, kpadB);
+    if (!sweepB) return set_err(c, GMGM_E_SHAPE, "no sweep variant for r = %lld", (long long)r);
+    void *candB, *wpB;
+    GMGM_TRY(ws_get(c, WS_CAND2, (size_t)std::max<long long>(totB, 1) * 8, &candB));
+    const int64_t wtB = ceil_div(h_fail, 32);
+    GMGM_TRY(ws_get(c, WS_WP2, (size_t)wtB * unitsB * 64 * 16, &wpB));
+    const u32x4* vpB = A.vp;
+    if (precB != prec) {
+      void* v2;
+      GMGM_TRY(ws_get(c, WS_VP2, (size_t)n_vtiles * unitsB * 64 * 16, &v2));
+      const int64_t tv = (int64_t)n_vtiles * 32 * (kpadB / chunk_elems(precB));
+      hipLaunchKernelGGL(repack_kernel<P_BF16>, dim3((unsigned)ceil_div(tv, 256)), dim3(256), 0, st, V, psi,
+                         (int64_t)0, n, (int64_t)n_vtiles * 32, (int)r, kpadB, false, ev, true, (const int*)nullptr,
+                         (const int*)nullptr, (u32x4*)v2);
+      vpB = (const u32x4*)v2;
+    }
+    const int64_t twB = wtB * 32 * (kpadB / chunk_elems(precB));
+    if (precB == P_F32)
+      hipLaunchKernelGGL(repack_kernel<P_F32>, dim3((unsigned)ceil_div(twB, 256)), dim3(256), 0, st, V, psi,
+                         (int64_t)0, n, wtB * 32, (int)r, kpadB, true, ew, false, (const int*)fail_rows,
+                         (const int*)fail_count, (u32x4*)wpB);
+    else
+      hipLaunchKernelGGL(repack_kernel<P_BF16>, dim3((unsigned)ceil_div(twB, 256)), dim3(256), 0, st, V, psi,
+                         (int64_t)0, n, wtB * 32, (int)r, kpadB, true, ew, false, (const int*)fail_rows,
+                         (const int*)fail_count, (u32x4*)wpB);
+    SweepArgs sb = sa;
+    sb.Vp = vpB;
+    sb.Wp = (const u32x4*)wpB;
+    sb.cval = (float*)candB;
+    sb.cidx = (int*)((char*)candB + (size_t)std::max<long long>(totB, 1) * 4);
+    sb.row_list = fail_rows;
+    sb.row_count = fail_count;
+    sb.n_wtiles = (int)wtB;
+    sb.cprec = cprec_for(precB, kpadB);
+    sb.toff = toffB;
+    sb.tcount = tcountB;
+    const int64_t gxB = ceil_div(wtB, (int64_t)SW_WAVES * 2);
+    hipEvent_t t1 = timing_start(c);
+    sweepB<<<dim3((unsigned)gxB, 1), dim3(SW_THREADS), 0, st>>>(sb);
+    timing_stop(c, t1);
+    GMGM_HIP(c, hipGetLastError());
+    ThrArgs tb = ta;
+    tb.cidx = sb.cidx;
+    tb.tcount = tcountB;
+    tb.list = fail_list;
+    tb.toff = toffB;
+    tb.rows = h_fail;
+    tb.fail_list = fail2;
+    tb.fail_rows = nullptr;
+    tb.fail_count = fail_count2;
+    hipLaunchKernelGGL(thr_verify_kernel, dim3((unsigned)ceil_div(h_fail, 4)), dim3(256), 0, st, tb);
+    // ---- rows whose listed re-sweep still overflowed: exact scan
+    int h_fail2 = 0;
+    GMGM_HIP(c, hipMemcpyAsync(&h_fail2, fail_count2, 4, hipMemcpyDeviceToHost, st));
+    GMGM_HIP(c, hipStreamSynchronize(st));
+    if (h_fail2 > 0)
+      hipLaunchKernelGGL(thr_exact_kernel, dim3((unsigned)std::min(h_fail2, 4096)), dim3(256), 0, st, tb);
+  }
+  hipLaunchKernelGGL(thr_scan_kernel, dim3(1), dim3(1024), 0, st, kept_n, rows, row_ptr_out, info);
+  long long h_info[2];
+  GMGM_HIP(c, hipMemcpyAsync(h_info, info, 16, hipMemcpyDeviceToHost, st));
+  GMGM_HIP(c, hipStreamSynchronize(st));
+  GMGM_TRY(gmgm_sync(c));   // non-finite inputs found by prep
+  *nnz_out = (int64_t)h_info[0];
+  if (max_per_row > 0 && h_info[1] > max_per_row)
+    return set_err(c, GMGM_E_OVERFLOW, "a row keeps %lld entries, more than max_per_row = %d", h_info[1], max_per_row);
+  if (h_info[0] > capacity)
+    return set_err(c, GMGM_E_OVERFLOW, "%lld entries exceed the capacity %lld", h_info[0], (long long)capacity);
+  hipLaunchKernelGGL(thr_gather_kernel, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, st, pool_j, pool_v, pool_off,
+                     kept_n, row_ptr_out, rows, col_out, val_out);
+  GMGM_HIP(c, hipGetLastError());
+  return GMGM_OK;
+}
+
+// Upper normal quantile z with 0.5 erfc(z / sqrt 2) = p, 0 < p <= 0.5: the
+// rational starting value of Abramowitz and Stegun 26.2.23, then Newton steps
+// on the tail itself (quadratic convergence to double precision).
+static double upper_normal_quantile(double p) {
+  const double t = std::sqrt(-2.0 * std::log(p));
+  double z = t - (2.515517 + 0.802853 * t + 0.010328 * t * t) /
+                     (1.0 + 1.432788 * t + 0.189269 * t * t + 0.001308 * t * t * t);
+  for (int it = 0; it < 8; ++it) {
+    const double tail = 0.5 * std::erfc(z / std::sqrt(2.0));
+    const double dens = std::exp(-0.5 * z * z) / std::sqrt(2.0 * M_PI);
+    const double step = (tail - p) / dens;
+    z += step;
+    if (std::fabs(step) <= 1e-15 * std::fabs(z)) break;
+  }
+  return z;
+}
+
+extern "C" gmgm_status gmgm_significance_threshold(gmgm_ctx_t c, int64_t d_l, int32_t n_mod, const double* d_all,
+                                                   const double* trace_s, double alpha, double n_tests,
+                                                   double* thr_out) {
+  // host arithmetic only: a null context is allowed (errors are then returned
+  // without a message)
+#define SIG_ERR(code, ...) (c ? set_err(c, code, __VA_ARGS__) : code)
+  if (d_l < 2 || n_mod < 1 || !d_all || !trace_s || !thr_out)
+    return SIG_ERR(GMGM_E_ARG, "need d_l >= 2, n_mod >= 1 and non-null arrays");
+  if (!(alpha > 0.0 && alpha < 1.0)) return SIG_ERR(GMGM_E_DOMAIN, "alpha must be in (0, 1)");
+  const double m = n_tests > 0.0 ? n_tests : 0.5 * (double)d_l * (double)(d_l - 1);
+  double denom = 0.0;
+  for (int g = 0; g < n_mod; ++g) {
+    if (!(d_all[g] > 0.0) || !(trace_s[g] > 0.0) || !std::isfinite(d_all[g]) || !std::isfinite(trace_s[g]))
+      return SIG_ERR(GMGM_E_DOMAIN, "modality %d: d_all and trace_s must be positive and finite", g);
+    const double s2 = trace_s[g] / d_all[g];     // the null model's variance
+    denom += d_all[g] * s2 * s2;
+  }
+  const double p = alpha / (2.0 * m);
+  if (!(p > 0.0)) return SIG_ERR(GMGM_E_DOMAIN, "alpha / (2 n_tests) underflows");
+  *thr_out = 2.0 * upper_normal_quantile(p) * std::sqrt((double)d_l / denom);
+  return GMGM_OK;
+#undef SIG_ERR
 }

@@ -56,6 +56,12 @@ struct SweepArgs {
   int64_t w_lo;
   double cprec;
   int k;
+  // threshold mode: keep |Psi_ij| >= thr; cval / cidx hold capt candidates per
+  // (slot, split, sub-list), tcount their counts (beyond capt: overflowed)
+  double thr;
+  int capt;
+  int* tcount;
+  const long long* toff;  // threshold mode, listed rows: candidate offsets per slot (null: slot * capt)
 };
 
 template <int PREC>
@@ -124,14 +130,26 @@ __host__ __device__ constexpr int sweep_tps(int UNITS) { return 44 / UNITS > 0 ?
 constexpr int SW_Q = 16;  // append-queue entries per lane (own list), in LDS
 static_assert(SW_Q >= 16, "the slow path appends up to 16 values per half row after a flush");
 
+// The largest float below f (f finite or infinite).
+__device__ inline float float_below(float f) {
+  if (f == -INFINITY) return f;
+  if (f == 0.0f) return -__int_as_float(1);
+  const int b = __float_as_int(f);
+  return __int_as_float(f > 0.0f ? b - 1 : b + 1);
+}
+
 struct QEntry {
   float v;
   int j;
 };
 
-template <int PREC, int UNITS, int TI, int C>
+// THR selects the threshold mode: the per-row threshold is fixed (the
+// requested one lowered by the row's rounding bound) and every value above it
+// is written straight to the row's candidate region; no lists are kept.
+template <int PREC, int UNITS, int TI, int C, bool THR = false>
 __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   static_assert(TI == 1 || TI == 2, "one or two row tiles per wave");
+  static_assert(!THR || TI == 2, "threshold mode keeps whole rows per lane");
   constexpr bool PAIR = sweep_pairs(TI);
   constexpr int NSUB = sweep_nsub(TI);
   constexpr int TPS = sweep_tps(UNITS);
@@ -209,10 +227,43 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   const int myrow_own = PAIR ? myrow[h == 0 ? 0 : TI - 1] : myrow[0];
   const int ew_own = PAIR ? ewt[h == 0 ? 0 : TI - 1] : ewt[0];
   // 2 beta of the own row (0 for lanes without a row)
-  const float beta2 = myrow_own >= 0
-      ? (float)(2.0 * a.cprec * a.wnorm[myrow_own - a.w_lo] * (double)__uint_as_float(*a.vmax_bits))
-      : 0.0f;
+  const double beta_own = myrow_own >= 0
+      ? a.cprec * a.wnorm[myrow_own - a.w_lo] * (double)__uint_as_float(*a.vmax_bits)
+      : 0.0;
+  const float beta2 = (float)(2.0 * beta_own);
   float own_tau = -1.0f;   // max(lv[C-1], lv[k-1] - beta2), refreshed by flush
+  // the candidate region this lane writes in threshold mode
+  const int to = PAIR ? h : 0;
+  const int sub = PAIR ? 0 : h;
+  int64_t tbase = 0;
+  int tcap = 0;         // candidate room of the own row (threshold mode)
+  if constexpr (THR) {
+    if (slot[to] >= 0) {
+      tbase = a.toff ? a.toff[slot[to]] : (((int64_t)slot[to] * a.S + blockIdx.y) * NSUB + sub) * a.capt;
+      tcap = a.toff ? (int)(a.toff[slot[to] + 1] - a.toff[slot[to]]) : a.capt;
+    }
+  }
+  int tcnt = 0;
+  if constexpr (THR) {
+    // candidates: approximate |Psi| >= thr - beta (every exact |Psi| >= thr is
+    // one); as a float compared with '>': the value just below thr - beta
+    // rounded down.  Lanes without a written row take nothing.
+    own_tau = INFINITY;
+    if (slot[to] >= 0) {
+      const double lo = a.thr - beta_own;
+      float f = (float)lo;
+      if ((double)f > lo) f = float_below(f);
+      own_tau = float_below(f);
+    }
+    if constexpr (PAIR) {
+      float x = own_tau, y = own_tau;
+      swap_halves(x, y);
+      tau[0] = x;
+      tau[TI - 1] = y;
+    } else {
+      tau[0] = own_tau;
+    }
+  }
 
   // Merge every lane's queue into its list (all lanes at once), then refresh the
   // cached thresholds.  Wave-uniform.  A lane reads only the entries it wrote,
@@ -353,6 +404,39 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
           if constexpr (PREC == P_FP8) sc = ew_own + evt;
           float own = own_tau;
           if constexpr (PREC == P_FP8) own = __builtin_ldexpf(own, -sc);
+          if constexpr (THR) {
+            // threshold mode: both halves of the own row, emitted in ascending
+            // column order (group g of half 0 holds columns 8g..8g+3, of half
+            // 1 columns 8g+4..8g+7)
+            float x[2][16];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+              for (int v = 0; v < 16; ++v) {
+                const float y = fabsf(hh ? acc[TI - 1][v] : acc[0][v]);
+                const int o = acc_row(v, hh);
+                x[hh][v] = (masked && (o >= lim || o == myrow_own - j0)) ? -INFINITY : y;
+              }
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+              for (int hh = 0; hh < 2; ++hh) {
+                const float gmx = fmaxf(fmaxf(x[hh][4 * g], x[hh][4 * g + 1]), fmaxf(x[hh][4 * g + 2], x[hh][4 * g + 3]));
+                if (!__ballot(gmx > own)) continue;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  const int v = 4 * g + e;
+                  float xv = x[hh][v];
+                  const bool take = xv > own;
+                  if constexpr (PREC == P_FP8) xv = __builtin_ldexpf(xv, sc);
+                  if (take && tcnt < tcap) {
+                    a.cval[tbase + tcnt] = xv;
+                    a.cidx[tbase + tcnt] = j0 + acc_row(v, hh);
+                  }
+                  tcnt += take ? 1 : 0;
+                }
+              }
+          } else
 #pragma unroll
           for (int hh = 0; hh < (PAIR ? 2 : 1); ++hh) {
             if (PAIR && !__ballot((hh ? mh1 : mh0) > own)) continue;
@@ -422,11 +506,13 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   }
 
   if (!active) return;
+  if constexpr (THR) {
+    if (slot[to] >= 0) a.tcount[((int64_t)slot[to] * a.S + blockIdx.y) * NSUB + sub] = tcnt;
+    return;
+  }
   flush();
   // the list of this lane: row l32 of tile h (pairs) or this lane's half row
-  const int to = PAIR ? h : 0;
   if (slot[to] >= 0) {
-    const int sub = PAIR ? 0 : h;
     const int64_t base = (((int64_t)slot[to] * a.S + blockIdx.y) * NSUB + sub) * C;
 #pragma unroll
     for (int s = 0; s < C; ++s) {
@@ -452,5 +538,6 @@ SweepFn pick_sweep_bf16_c16(int kpad);
 SweepFn pick_sweep_bf16_c32(int kpad);
 SweepFn pick_sweep_fp8_c16(int kpad);
 SweepFn pick_sweep_fp8_c32(int kpad);
+SweepFn pick_sweep_thr(int prec, int kpad);   // threshold mode
 
 }  // namespace gmgm_rc
