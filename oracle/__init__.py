@@ -10,8 +10,9 @@ partial eigendecomposition and the cell-axis factor (Algorithm 1, Theorem 1),
 the eigenvalue maximum-likelihood estimate (model equation, eigenvalue-gradient
 Proposition, Existence lemma), the eigen-recomposition with per-row top-k
 thresholding (Algorithm 1's final loop and the complexity appendix), the
-significance threshold of Theorem 3 and the thresholded graph it defines, and
-the learned warm start's multilayer perceptron.
+significance threshold of Theorem 3 and the thresholded graph it defines, the
+Nonparanormal Skeptic kept sparse (input-sparsity appendix), and the learned
+warm start's multilayer perceptron.
 
 Readings of passages that are silent or ambiguous are stated in the docstring
 of the function that takes them.
@@ -24,10 +25,11 @@ from .topk import topk_row, topk_csr, near_tie_rows
 from . import warmstart
 from . import range_finder
 from . import significance
+from . import skeptic
 
 __all__ = [
     "gram_dense", "gram_csr", "eigh_desc", "numerical_rank", "cell_factor",
     "Problem", "nll", "grad", "solve_eigs", "alg1_gradient_descent", "default_eps",
     "psi_dense", "psi_rows", "psi_blockwise", "topk_row", "topk_csr", "near_tie_rows",
-    "warmstart", "range_finder", "significance",
+    "warmstart", "range_finder", "significance", "skeptic",
 ]
