@@ -238,6 +238,49 @@ gmgm_status gmgm_sketch(gmgm_ctx_t ctx, int64_t n, int64_t p, int64_t nnz, const
                         const int32_t* col, const float* val, const double* evecs, int64_t ldv,
                         const double* evals, int64_t r, float* U);
 
+/*
+ * Nonparanormal Skeptic of a sparse matrix, kept sparse ("Preserving input
+ * sparsity": the rank-based Gaussian copula transform used before the Gram in
+ * the paper's real-data runs).  Every column g of the n x p CSR matrix X
+ * (cells x genes) is transformed marginally across its n entries, implicit
+ * zeros included:
+ *   f(x) = Phi^-1(rank(x) / (n + 1)),  rank(x) = 1 + #{entries of the column below x}
+ * (ties share the smallest rank).  All zeros of a column map to z_g, so the
+ * transformed matrix is S + 1 z^T with S of X's sparsity pattern.
+ *
+ *   n, p, nnz, row_ptr, col, val   X as in gmgm_gram (val NULL: all ones);
+ *               nnz < 2^32.
+ *   val_out     nnz FP32 (device): S at X's entries, f(x_ig) - z_g (0 where
+ *               x_ig = 0), in X's entry order.
+ *   z_out       p FP64 (device): z_g = f(0) of column g.
+ *   csum_out    p FP64 (device): column sums of S (for gmgm_gram_shifted).
+ * Synchronises once (malformed CSR -> GMGM_E_SHAPE, non-finite values ->
+ * GMGM_E_DOMAIN before anything is sorted).  Uses rocPRIM's segmented radix
+ * sort for the per-column ordering.
+ */
+gmgm_status gmgm_skeptic(gmgm_ctx_t ctx, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                         const int32_t* col, const float* val, float* val_out, double* z_out,
+                         double* csum_out);
+
+/*
+ * Gram of X + 1 z^T (the transformed matrix of gmgm_skeptic) from X's CSR:
+ *   G = X^T X + c z^T + z c^T + n z z^T,  c = X^T 1 (csum),
+ * the rank-two correction added in FP64 before rounding.  Arguments as
+ * gmgm_gram, plus z and csum (p FP64 each, device).
+ */
+gmgm_status gmgm_gram_shifted(gmgm_ctx_t ctx, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                              const int32_t* col, const float* val, const double* z, const double* csum,
+                              float* G);
+
+/*
+ * Cell factor of X + 1 z^T: U = (X + 1 z^T) V[:, :r] diag(e)^-1/2, i.e.
+ * gmgm_sketch's X V diag(e)^-1/2 plus the row z^T V[:, :r] diag(e)^-1/2 on
+ * every row.  Arguments as gmgm_sketch, plus z (p FP64, device).
+ */
+gmgm_status gmgm_sketch_shifted(gmgm_ctx_t ctx, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                                const int32_t* col, const float* val, const double* evecs, int64_t ldv,
+                                const double* evals, int64_t r, const double* z, float* U);
+
 /* A CSR matrix (all arrays device, caller-owned): row_ptr has n_rows + 1
  * int64 entries, col and val nnz entries; val NULL means all ones. */
 typedef struct {

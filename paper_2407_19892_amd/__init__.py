@@ -68,6 +68,9 @@ SIGNATURES = {
                                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                                    ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "gmgm_gram": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
+    "gmgm_gram_shifted": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P]),
+    "gmgm_sketch_shifted": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P]),
+    "gmgm_skeptic": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "gmgm_eigh_small": (ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.POINTER(_I64)]),
     "gmgm_sketch": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _I64, _P, _I64, _P]),
     "gmgm_ws_param_count": (_I64, []),
@@ -320,13 +323,40 @@ def _csr_args(row_ptr, col, val, n):
     return _ptr(row_ptr), _ptr(col), (_ptr(val) if val is not None else None), col.numel()
 
 
-def gram(row_ptr, col, val, n: int, p: int, out=None, check: bool = True):
-    """G = X^T X (p x p, FP32) of the CSR matrix X (n x p); see gmgm_gram."""
+@dataclass
+class SkepticResult:
+    val: "object"      # S's values at X's entries (FP32)
+    z: "object"        # per-column value of the zeros (FP64)
+    csum: "object"     # column sums of S (FP64)
+
+
+def skeptic(row_ptr, col, val, n: int, p: int) -> SkepticResult:
+    """Nonparanormal Skeptic of the CSR matrix X kept sparse: X~ = S + 1 z^T
+    (see gmgm_skeptic).  S shares X's row_ptr and col."""
+    import torch
+    rp, cp, vp, nnz = _csr_args(row_ptr, col, val, n)
+    dev = row_ptr.device
+    out = torch.empty(max(nnz, 1), dtype=torch.float32, device=dev)
+    z = torch.empty(p, dtype=torch.float64, device=dev)
+    cs = torch.empty(p, dtype=torch.float64, device=dev)
+    c = context(dev.index)
+    _check(c, load().gmgm_skeptic(c, n, p, nnz, rp, cp, vp, _ptr(out), _ptr(z), _ptr(cs)))
+    return SkepticResult(out[:nnz], z, cs)
+
+
+def gram(row_ptr, col, val, n: int, p: int, out=None, check: bool = True, shift=None):
+    """G = X^T X (p x p, FP32) of the CSR matrix X (n x p); see gmgm_gram.
+    With shift = (z, csum) (e.g. from skeptic), the Gram of X + 1 z^T
+    (gmgm_gram_shifted)."""
     import torch
     rp, cp, vp, nnz = _csr_args(row_ptr, col, val, n)
     G = torch.empty(p, p, dtype=torch.float32, device=row_ptr.device) if out is None else out
     c = context(row_ptr.device.index)
-    _check(c, load().gmgm_gram(c, n, p, nnz, rp, cp, vp, _ptr(G)))
+    if shift is None:
+        _check(c, load().gmgm_gram(c, n, p, nnz, rp, cp, vp, _ptr(G)))
+    else:
+        z, cs = shift
+        _check(c, load().gmgm_gram_shifted(c, n, p, nnz, rp, cp, vp, _ptr(z), _ptr(cs), _ptr(G)))
     if check:
         _check(c, load().gmgm_sync(c))
     return G
@@ -348,9 +378,10 @@ def eigh_small(G):
     return w, Vt, rank.value
 
 
-def sketch(row_ptr, col, val, n: int, p: int, Vt, evals, r: int, out=None, check: bool = True):
+def sketch(row_ptr, col, val, n: int, p: int, Vt, evals, r: int, out=None, check: bool = True, z=None):
     """U = X V[:, :r] diag(e[:r])^-1/2 (n x r FP32).  Vt is the column-major
-    eigenvector storage returned by eigh_small (row j = eigenvector j)."""
+    eigenvector storage returned by eigh_small (row j = eigenvector j).  With z,
+    the factor of X + 1 z^T (gmgm_sketch_shifted)."""
     import torch
     rp, cp, vp, nnz = _csr_args(row_ptr, col, val, n)
     if not (Vt.is_cuda and Vt.dtype == torch.float64 and Vt.is_contiguous() and Vt.dim() == 2
@@ -360,7 +391,11 @@ def sketch(row_ptr, col, val, n: int, p: int, Vt, evals, r: int, out=None, check
         raise TypeError("evals must be a float64 device tensor with >= r entries")
     U = torch.empty(n, r, dtype=torch.float32, device=row_ptr.device) if out is None else out
     c = context(row_ptr.device.index)
-    _check(c, load().gmgm_sketch(c, n, p, nnz, rp, cp, vp, _ptr(Vt), Vt.shape[1], _ptr(evals), r, _ptr(U)))
+    if z is None:
+        _check(c, load().gmgm_sketch(c, n, p, nnz, rp, cp, vp, _ptr(Vt), Vt.shape[1], _ptr(evals), r, _ptr(U)))
+    else:
+        _check(c, load().gmgm_sketch_shifted(c, n, p, nnz, rp, cp, vp, _ptr(Vt), Vt.shape[1], _ptr(evals), r,
+                                             _ptr(z), _ptr(U)))
     if check:
         _check(c, load().gmgm_sync(c))
     return U

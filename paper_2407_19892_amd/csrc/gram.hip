@@ -176,9 +176,13 @@ __global__ void __launch_bounds__(256) densify_kernel(const int64_t* __restrict_
 }
 
 // G (p x p, row-major FP32) from the FP64 split partials: sum the splits in
-// order, take the upper triangle's value for both (a, b) and (b, a).
+// order, take the upper triangle's value for both (a, b) and (b, a).  With a
+// shift z (the Gram of X + 1 z^T, cs = X's column sums): + cs_a z_b + z_a cs_b
+// + n z_a z_b, in FP64 before rounding.
 __global__ void __launch_bounds__(256) gram_finish_kernel(const double* __restrict__ P, int n_split,
                                                           int64_t pp, int64_t p,
+                                                          const double* __restrict__ zs,
+                                                          const double* __restrict__ cs, double nrows,
                                                           float* __restrict__ G) {
   __shared__ double t[32][33];
   const int A = blockIdx.y, B = blockIdx.x;
@@ -198,6 +202,7 @@ __global__ void __launch_bounds__(256) gram_finish_kernel(const double* __restri
     if (A < B) v = t[r][tx];
     else if (A > B) v = t[tx][r];
     else v = r <= tx ? t[r][tx] : t[tx][r];
+    if (zs) v += cs[a] * zs[b] + zs[a] * cs[b] + nrows * zs[a] * zs[b];
     G[a * p + b] = (float)v;
   }
 }
@@ -211,10 +216,8 @@ inline unsigned grid_for(int64_t n, int per_block) {
 
 using namespace gmgm_gr;
 
-extern "C" gmgm_status gmgm_gram(gmgm_ctx_t c, int64_t n, int64_t p, int64_t nnz,
-                                 const int64_t* row_ptr, const int32_t* col, const float* val,
-                                 float* G) {
-  GMGM_CHECK_CTX(c);
+static gmgm_status gram_impl(gmgm_ctx* c, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                             const int32_t* col, const float* val, const double* zs, const double* cs, float* G) {
   if (n < 1 || p < 1 || p > 65536 || nnz < 0)
     return set_err(c, GMGM_E_SHAPE, "need n >= 1, 1 <= p <= 65536, nnz >= 0 (got n=%lld p=%lld nnz=%lld)",
                    (long long)n, (long long)p, (long long)nnz);
@@ -262,7 +265,22 @@ extern "C" gmgm_status gmgm_gram(gmgm_ctx_t c, int64_t n, int64_t p, int64_t nnz
     timing_stop(c, ev);
   }
   const unsigned g32 = (unsigned)((p + 31) / 32);
-  hipLaunchKernelGGL(gram_finish_kernel, dim3(g32, g32), dim3(256), 0, st, P, n_split, pp, p, G);
+  hipLaunchKernelGGL(gram_finish_kernel, dim3(g32, g32), dim3(256), 0, st, P, n_split, pp, p, zs, cs, (double)n, G);
   GMGM_HIP(c, hipGetLastError());
   return GMGM_OK;
+}
+
+extern "C" gmgm_status gmgm_gram(gmgm_ctx_t c, int64_t n, int64_t p, int64_t nnz,
+                                 const int64_t* row_ptr, const int32_t* col, const float* val,
+                                 float* G) {
+  GMGM_CHECK_CTX(c);
+  return gram_impl(c, n, p, nnz, row_ptr, col, val, nullptr, nullptr, G);
+}
+
+extern "C" gmgm_status gmgm_gram_shifted(gmgm_ctx_t c, int64_t n, int64_t p, int64_t nnz,
+                                         const int64_t* row_ptr, const int32_t* col, const float* val,
+                                         const double* z, const double* csum, float* G) {
+  GMGM_CHECK_CTX(c);
+  if (!z || !csum) return set_err(c, GMGM_E_ARG, "null shift pointer");
+  return gram_impl(c, n, p, nnz, row_ptr, col, val, z, csum, G);
 }

@@ -65,15 +65,15 @@ template <int W>
 __global__ void __launch_bounds__(256) spmm_kernel(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                    const float* __restrict__ val, int64_t nnz, int64_t n, int64_t p,
                                                    const float* __restrict__ Bp, int r, float* __restrict__ U,
-                                                   int* __restrict__ status) {
+                                                   const double* __restrict__ wsh, int* __restrict__ status) {
   using T = typename Vec<W>::T;
   const int lane = threadIdx.x & 63;
   const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
   const int64_t b = rp[i], e = rp[i + 1];
-  double acc[W];
+  double acc[W];   // starts at the shift row (the rank-one part of X + 1 z^T) when given
 #pragma unroll
-  for (int q = 0; q < W; ++q) acc[q] = 0.0;
+  for (int q = 0; q < W; ++q) acc[q] = (wsh && lane * W + q < r) ? wsh[lane * W + q] : 0.0;
   bool badc = false, badv = false;
   if (b < 0 || e < b || e > nnz) {
     if (lane == 0) atomicCAS(status, 0, DEV_BADINDEX);
@@ -121,14 +121,24 @@ __global__ void __launch_bounds__(256) spmm_kernel(const int64_t* __restrict__ r
   }
 }
 
+// w = z^T Bp (r entries, FP64): the cell-factor row every cell gets from the
+// rank-one part 1 z^T of X + 1 z^T.  One thread per output column.
+__global__ void shift_row_kernel(const float* __restrict__ Bp, int64_t p, int rpad, int r,
+                                 const double* __restrict__ z, double* __restrict__ w) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= r) return;
+  double s = 0.0;
+  for (int64_t g = 0; g < p; ++g) s += z[g] * (double)Bp[g * rpad + j];
+  w[j] = s;
+}
+
 }  // namespace gmgm_sk
 
 using namespace gmgm_sk;
 
-extern "C" gmgm_status gmgm_sketch(gmgm_ctx_t c, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
-                                   const int32_t* col, const float* val, const double* evecs, int64_t ldv,
-                                   const double* evals, int64_t r, float* U) {
-  GMGM_CHECK_CTX(c);
+static gmgm_status sketch_impl(gmgm_ctx* c, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                               const int32_t* col, const float* val, const double* evecs, int64_t ldv,
+                               const double* evals, int64_t r, const double* z, float* U) {
   if (n < 1 || p < 1 || nnz < 0 || r < 1 || r > 256 || r > p || ldv < p)
     return set_err(c, GMGM_E_SHAPE, "need n >= 1, p >= 1, nnz >= 0, 1 <= r <= min(p, 256), ldv >= p");
   if (!row_ptr || !evecs || !evals || !U || (nnz > 0 && !col)) return set_err(c, GMGM_E_ARG, "null pointer argument");
@@ -142,18 +152,41 @@ extern "C" gmgm_status gmgm_sketch(gmgm_ctx_t c, int64_t n, int64_t p, int64_t n
   const int64_t tot = p * rpad;
   hipLaunchKernelGGL(panel_kernel, dim3((unsigned)std::min<int64_t>(65536, (tot + 255) / 256)), dim3(256), 0, st,
                      evecs, ldv, evals, p, (int)r, rpad, Bp, c->dev_status);
+  double* wsh = nullptr;
+  if (z) {
+    void* ww;
+    GMGM_TRY(ws_get(c, WS_SKEP0, (size_t)r * sizeof(double) + 64, &ww));
+    wsh = (double*)ww;
+    hipLaunchKernelGGL(shift_row_kernel, dim3((unsigned)((r + 255) / 256)), dim3(256), 0, st, Bp, p, rpad, (int)r,
+                       z, wsh);
+  }
   const dim3 grid((unsigned)((n + 3) / 4));
   hipEvent_t ev = timing_start(c);
   if (W == 1)
     hipLaunchKernelGGL(spmm_kernel<1>, grid, dim3(256), 0, st, row_ptr, col, val, nnz, n, p, Bp, (int)r, U,
-                       c->dev_status);
+                       wsh, c->dev_status);
   else if (W == 2)
     hipLaunchKernelGGL(spmm_kernel<2>, grid, dim3(256), 0, st, row_ptr, col, val, nnz, n, p, Bp, (int)r, U,
-                       c->dev_status);
+                       wsh, c->dev_status);
   else
     hipLaunchKernelGGL(spmm_kernel<4>, grid, dim3(256), 0, st, row_ptr, col, val, nnz, n, p, Bp, (int)r, U,
-                       c->dev_status);
+                       wsh, c->dev_status);
   timing_stop(c, ev);
   GMGM_HIP(c, hipGetLastError());
   return GMGM_OK;
+}
+
+extern "C" gmgm_status gmgm_sketch(gmgm_ctx_t c, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                                   const int32_t* col, const float* val, const double* evecs, int64_t ldv,
+                                   const double* evals, int64_t r, float* U) {
+  GMGM_CHECK_CTX(c);
+  return sketch_impl(c, n, p, nnz, row_ptr, col, val, evecs, ldv, evals, r, nullptr, U);
+}
+
+extern "C" gmgm_status gmgm_sketch_shifted(gmgm_ctx_t c, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                                           const int32_t* col, const float* val, const double* evecs, int64_t ldv,
+                                           const double* evals, int64_t r, const double* z, float* U) {
+  GMGM_CHECK_CTX(c);
+  if (!z) return set_err(c, GMGM_E_ARG, "null shift pointer");
+  return sketch_impl(c, n, p, nnz, row_ptr, col, val, evecs, ldv, evals, r, z, U);
 }
