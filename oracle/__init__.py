@@ -11,8 +11,9 @@ the eigenvalue maximum-likelihood estimate (model equation, eigenvalue-gradient
 Proposition, Existence lemma), the eigen-recomposition with per-row top-k
 thresholding (Algorithm 1's final loop and the complexity appendix), the
 significance threshold of Theorem 3 and the thresholded graph it defines, the
-Nonparanormal Skeptic kept sparse (input-sparsity appendix), and the learned
-warm start's multilayer perceptron.
+Nonparanormal Skeptic kept sparse (input-sparsity appendix), the eigenvalue
+estimate for modalities of three or more axes (tensor-variate data), and the
+learned warm start's multilayer perceptron.
 
 Readings of passages that are silent or ambiguous are stated in the docstring
 of the function that takes them.
@@ -26,10 +27,11 @@ from . import warmstart
 from . import range_finder
 from . import significance
 from . import skeptic
+from . import solver_tensor
 
 __all__ = [
     "gram_dense", "gram_csr", "eigh_desc", "numerical_rank", "cell_factor",
     "Problem", "nll", "grad", "solve_eigs", "alg1_gradient_descent", "default_eps",
     "psi_dense", "psi_rows", "psi_blockwise", "topk_row", "topk_csr", "near_tie_rows",
-    "warmstart", "range_finder", "significance", "skeptic",
+    "warmstart", "range_finder", "significance", "skeptic", "solver_tensor",
 ]

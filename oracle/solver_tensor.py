@@ -1,0 +1,227 @@
+"""Eigenvalue maximum-likelihood estimate for modalities of any number of
+axes (tensor-variate data).  Test infrastructure only.
+
+The model equation for a modality gamma with axes l_1..l_K: with the
+eigenvectors fixed to those of the S_l (Theorem 1), the Kronecker sum of the
+axes' precisions has eigenvalues lambda_{l_1,i_1} + ... + lambda_{l_K,i_K} over
+all index tuples (the derivation appendix: r_forall = prod r_l), so
+
+    NLL = 1/2 [ sum_l sum_i E_l,i lambda_l,i
+                - sum_gamma sum_{tuples of gamma} log(sum_{l in gamma} lambda_l,i_l) ]
+
+and the eigenvalue-gradient Proposition gives
+
+    dNLL/dlambda_l,i = 1/2 ( E_l,i - sum_{gamma containing l} sum_{tuples with i_l = i} 1/s ),
+
+with s the tuple's sum.  The Hessian has a diagonal block per axis and, for
+every two axes of a modality, the cross block sum over the remaining axes of
+1/2 s^-2.  Two-axis modalities reduce this to the pair model of
+``oracle.solver``.
+
+Method, readings and stopping rule as ``oracle.solver`` (box lambda >= eps,
+scaled KKT, projected Newton with LM damping rho = min(1e-2, KKT), Armijo
+along the projection arc, a shrink limit of STEP_SHRINK per step for free
+coordinates, the start's gauge restored along flat directions), with the
+Newton system solved densely (the Schur complement of the pair solver needs
+diagonal leaf blocks, which axes of a three-axis modality do not have).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .solver import default_eps
+
+STEP_SHRINK = 64.0
+
+
+@dataclass
+class TensorProblem:
+    E: list                      # per axis: float64 array, descending, positive
+    modalities: list             # list of tuples of distinct axes (length >= 2)
+    eps: list = field(default=None)
+
+    def __post_init__(self):
+        self.E = [np.asarray(e, dtype=np.float64) for e in self.E]
+        if self.eps is None:
+            self.eps = default_eps(self.E)
+        self.eps = [float(x) for x in self.eps]
+        for e in self.E:
+            if e.ndim != 1 or e.size == 0 or not np.all(e > 0) or not np.all(np.isfinite(e)):
+                raise ValueError("every E_l must be a nonempty positive finite vector")
+        self.modalities = [tuple(int(a) for a in m) for m in self.modalities]
+        for m in self.modalities:
+            if len(m) < 2 or len(set(m)) != len(m) or not all(0 <= a < len(self.E) for a in m):
+                raise ValueError("bad modality")
+
+    @property
+    def n_axes(self):
+        return len(self.E)
+
+    @property
+    def ranks(self):
+        return [e.size for e in self.E]
+
+
+def _sums(lam, m):
+    """The tuple sums of modality m as an array of shape (r_{m_0}, ..., r_{m_K-1})."""
+    K = len(m)
+    s = 0.0
+    for t, a in enumerate(m):
+        shape = [1] * K
+        shape[t] = -1
+        s = s + lam[a].reshape(shape)
+    return s
+
+
+def nll(lam, prob: TensorProblem) -> float:
+    lin = sum(float(np.dot(e, l)) for e, l in zip(prob.E, lam))
+    logs = sum(float(np.sum(np.log(_sums(lam, m)))) for m in prob.modalities)
+    return 0.5 * (lin - logs)
+
+
+def grad(lam, prob: TensorProblem):
+    g = [0.5 * e.copy() for e in prob.E]
+    for m in prob.modalities:
+        inv = 1.0 / _sums(lam, m)
+        for t, a in enumerate(m):
+            g[a] -= 0.5 * inv.sum(axis=tuple(u for u in range(len(m)) if u != t))
+    return g
+
+
+def hess_dense(lam, prob: TensorProblem):
+    off = np.concatenate([[0], np.cumsum(prob.ranks)])
+    H = np.zeros((off[-1], off[-1]))
+    for m in prob.modalities:
+        inv2 = 0.5 / _sums(lam, m) ** 2
+        K = len(m)
+        for t, a in enumerate(m):
+            d = inv2.sum(axis=tuple(u for u in range(K) if u != t))
+            H[off[a]:off[a + 1], off[a]:off[a + 1]] += np.diag(d)
+            for t2 in range(t + 1, K):
+                b = m[t2]
+                C = inv2.sum(axis=tuple(u for u in range(K) if u not in (t, t2)))
+                H[off[a]:off[a + 1], off[b]:off[b + 1]] += C
+                H[off[b]:off[b + 1], off[a]:off[a + 1]] += C.T
+    return H
+
+
+def flat_directions(prob: TensorProblem, rel_tol: float = 1e-12):
+    """Axis shifts c (sum over each modality's axes = 0) along which the NLL is constant."""
+    L = prob.n_axes
+    M = np.zeros((len(prob.modalities), L))
+    for t, m in enumerate(prob.modalities):
+        M[t, list(m)] = 1.0
+    _, s, Vt = np.linalg.svd(M)
+    rank = int(np.sum(s > 1e-12))
+    null = Vt[rank:]
+    tr = np.array([e.sum() for e in prob.E])
+    flats = [c for c in null if abs(0.5 * float(c @ tr)) <= rel_tol * 0.5 * float(np.abs(c) @ tr)]
+    r = np.array(prob.ranks, dtype=np.float64)
+    out = []
+    for c in flats:
+        for q in out:
+            c = c - (np.sum(r * c * q)) * q
+        nrm = math.sqrt(np.sum(r * c * c))
+        if nrm > 1e-12:
+            out.append(c / nrm)
+    return out
+
+
+def cold_start(prob: TensorProblem):
+    return [np.maximum(1.0 / e, eps) for e, eps in zip(prob.E, prob.eps)]
+
+
+def _fix_gauge(lam, prob, flats):
+    if not flats:
+        return lam
+    target = cold_start(prob)
+    lam = [l.copy() for l in lam]
+    for c in flats:
+        t = sum(c[l] * target[l].sum() for l in range(len(lam))) - sum(c[l] * lam[l].sum() for l in range(len(lam)))
+        for l in range(len(lam)):
+            lam[l] += t * c[l]
+    return lam
+
+
+def kkt_residual(lam, g, prob: TensorProblem) -> float:
+    res = 0.0
+    for l in range(prob.n_axes):
+        at = lam[l] <= prob.eps[l] * (1.0 + 1e-12)
+        r = np.where(at, np.maximum(0.0, -g[l]), np.abs(g[l])) / (0.5 * prob.E[l])
+        res = max(res, float(r.max()))
+    return res
+
+
+@dataclass
+class SolveResult:
+    lam: list
+    iters: int
+    kkt: float
+    converged: bool
+    n_pinned: list
+
+
+def solve_eigs(prob: TensorProblem, tol: float = 1e-12, max_iter: int = 200) -> SolveResult:
+    """Projected Newton from the cold start 1/E (the steps of oracle.solver with a
+    dense Newton system)."""
+    flats = flat_directions(prob)
+    lam = cold_start(prob)
+    eps = prob.eps
+    L = prob.n_axes
+    off = np.concatenate([[0], np.cumsum(prob.ranks)])
+    it = 0
+    g = grad(lam, prob)
+    kkt = kkt_residual(lam, g, prob)
+    for _round in range(3):
+        stalled = False
+        while kkt > tol and it < max_iter:
+            it += 1
+            f0 = nll(lam, prob)
+            H = hess_dense(lam, prob)
+            diag = [np.diag(H)[off[l]:off[l + 1]].copy() for l in range(L)]
+            active = []
+            for l in range(L):
+                reach = np.minimum(1e-3 * lam[l], g[l] / diag[l])
+                active.append((lam[l] - eps[l] <= reach) & (g[l] > 0))
+            free = [~a for a in active]
+            rho = min(1e-2, kkt)
+            F = np.concatenate(free)
+            gall = np.concatenate(g)
+            A = H[np.ix_(F, F)].copy()
+            A[np.diag_indices_from(A)] *= 1.0 + rho
+            dF = np.linalg.solve(A, -gall[F])
+            dall = np.zeros(off[-1])
+            dall[F] = dF
+            d = [dall[off[l]:off[l + 1]].copy() for l in range(L)]
+            for l in range(L):
+                d[l][active[l]] = -g[l][active[l]] / diag[l][active[l]]
+            floor = [np.where(active[l], eps[l], np.maximum(eps[l], lam[l] / STEP_SHRINK)) for l in range(L)]
+            alpha = 1.0
+            accepted = False
+            for _ in range(60):
+                trial = [np.maximum(lam[l] + alpha * d[l], floor[l]) for l in range(L)]
+                pred = 0.0
+                for l in range(L):
+                    pred += alpha * float(np.dot(g[l][free[l]], d[l][free[l]]))
+                    pred += float(np.dot(g[l][active[l]], trial[l][active[l]] - lam[l][active[l]]))
+                f1 = nll(trial, prob)
+                if f1 <= f0 + 1e-4 * pred or abs(pred) <= 1e-13 * (abs(f0) + 1.0):
+                    accepted = True
+                    break
+                alpha *= 0.5
+            if not accepted:
+                stalled = True
+                break
+            lam = trial
+            g = grad(lam, prob)
+            kkt = kkt_residual(lam, g, prob)
+        lam = [np.maximum(l, e) for l, e in zip(_fix_gauge(lam, prob, flats), eps)]
+        g = grad(lam, prob)
+        kkt = kkt_residual(lam, g, prob)
+        if kkt <= tol or it >= max_iter or stalled or not flats:
+            break
+    pinned = [int(np.sum(l <= e * (1 + 1e-12))) for l, e in zip(lam, eps)]
+    return SolveResult(lam, it, kkt, kkt <= tol, pinned)
