@@ -43,7 +43,6 @@ small cross-checks.
 """
 from __future__ import annotations
 
-import itertools
 import math
 from dataclasses import dataclass, field
 
@@ -235,16 +234,68 @@ def cold_start(prob: Problem):
     return [np.maximum(1.0 / e, eps) for e, eps in zip(prob.E, prob.eps)]
 
 
+def nearest_feasible_shift(t_star, flats, lam, eps, max_iter: int = 10_000):
+    """The gauge rule inside the box.  Moving lam by sum_q t_q c_q (c_q the flat
+    directions, orthonormal in the gauge metric) changes the q-th gauge value by
+    t_q and keeps every tuple sum, so the NLL and its gradient; it stays in the
+    box while min_i lam_l,i + u_l >= eps_l for every axis, u_l = sum_q t_q c_q,l.
+    Returns the t nearest to t_star (Euclidean) under those constraints.
+
+    The primal active-set method for a strictly convex quadratic program
+    (Nocedal and Wright, Numerical Optimization, Algorithm 16.3) from the
+    feasible point t = 0 (no move) with an empty working set: the step to the
+    minimiser on the working set's constraints taken as equalities, cut short
+    by the first constraint it would violate (which joins the set), and, at a
+    minimiser of the working set, the constraint with the most negative
+    multiplier leaves; it stops when every multiplier is non-negative."""
+    C = np.array(flats, dtype=np.float64)                  # q x L: column l is the normal of axis l
+    q, L = C.shape
+    m = np.array([float(x.min()) for x in lam])
+    b = np.array(eps, dtype=np.float64) - m                # need C^T t >= b
+    t_star = np.asarray(t_star, dtype=np.float64)
+    t = np.zeros(q)
+    W = []
+    for _ in range(max_iter):
+        g = t_star - t                                     # minus the objective's gradient
+        tol = 1e-12 * (float(np.linalg.norm(g)) + float(np.linalg.norm(t_star)) + 1e-300)
+        if W:
+            A = C[:, W]
+            mu = np.linalg.solve(A.T @ A, A.T @ g)         # g's component in the span of the normals
+            p = g - A @ mu if len(W) < q else np.zeros(q)  # q independent normals span everything
+        else:
+            mu, p = np.zeros(0), g
+        if np.linalg.norm(p) <= tol:
+            # minimiser on the working set; the multipliers of t - t_star = A lambda are -mu
+            size = mu * np.linalg.norm(C[:, W], axis=0) if W else mu
+            if not W or np.all(size <= tol):
+                return t
+            W.pop(int(np.argmax(size)))
+            continue
+        alpha, block = 1.0, -1
+        for l in range(L):
+            if l in W:
+                continue
+            ap = float(C[:, l] @ p)
+            if ap < 0.0:
+                a_l = max(0.0, float(C[:, l] @ t - b[l])) / -ap     # slack / rate of its decrease
+                if a_l < alpha:
+                    alpha, block = a_l, l
+        t = t + alpha * p
+        if block >= 0:
+            W.append(block)
+    raise RuntimeError("gauge projection did not terminate")
+
+
 def _fix_gauge(lam, prob, flats):
+    """Back to the gauge of the start 1/E along the flat directions, as near as the
+    box allows (nearest_feasible_shift)."""
     if not flats:
         return lam
     target = cold_start(prob)
-    lam = [l.copy() for l in lam]
-    for c in flats:
-        t = _gauge_value(target, c) - _gauge_value(lam, c)
-        for l in range(len(lam)):
-            lam[l] += t * c[l]
-    return lam
+    t_star = [_gauge_value(target, c) - _gauge_value(lam, c) for c in flats]
+    t = nearest_feasible_shift(t_star, flats, lam, prob.eps)
+    u = np.array(flats).T @ t
+    return [l + u[i] for i, l in enumerate(lam)]
 
 
 def kkt_residual(lam, g, prob: Problem) -> float:

@@ -32,7 +32,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .solver import default_eps
+from .solver import default_eps, nearest_feasible_shift
 
 STEP_SHRINK = 64.0
 
@@ -135,15 +135,15 @@ def cold_start(prob: TensorProblem):
 
 
 def _fix_gauge(lam, prob, flats):
+    """Back to the gauge of the start 1/E along the flat directions, as near as the
+    box allows (oracle.solver.nearest_feasible_shift)."""
     if not flats:
         return lam
     target = cold_start(prob)
-    lam = [l.copy() for l in lam]
-    for c in flats:
-        t = sum(c[l] * target[l].sum() for l in range(len(lam))) - sum(c[l] * lam[l].sum() for l in range(len(lam)))
-        for l in range(len(lam)):
-            lam[l] += t * c[l]
-    return lam
+    t_star = [sum(c[l] * (target[l].sum() - lam[l].sum()) for l in range(len(lam))) for c in flats]
+    t = nearest_feasible_shift(t_star, flats, lam, prob.eps)
+    u = np.array(flats).T @ t
+    return [l + u[i] for i, l in enumerate(lam)]
 
 
 def kkt_residual(lam, g, prob: TensorProblem) -> float:

@@ -96,3 +96,142 @@ def test_kkt_and_shared_axes_three_axis_graph():
     res = T.solve_eigs(prob)
     assert res.converged and res.kkt <= 1e-12
     assert all(np.all(l >= e) for l, e in zip(res.lam, prob.eps))
+
+
+def _spectra(shape, rank, seed, noise=0.3):
+    """Gram spectra of the unfoldings of a low-rank-plus-noise tensor (all axes
+    share the trace |X|^2, so every shift direction is flat)."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    fac = [rng.standard_normal((d, rank)) for d in shape]
+    X = np.zeros(shape)
+    for q in range(rank):
+        t = fac[0][:, q]
+        for f in fac[1:]:
+            t = np.multiply.outer(t, f[:, q])
+        X += t * 2.0 ** -q
+    X += noise * rng.standard_normal(shape)
+    out = []
+    for l in range(len(shape)):
+        U = np.moveaxis(X, l, 0).reshape(shape[l], -1)
+        out.append(oracle.eigh_desc(U @ U.T)[0])
+    return out
+
+
+def _projection_by_enumeration(t_star, C, b):
+    """Brute force: the feasible projection of t_star onto every affine set where
+    a linearly independent choice of constraints holds with equality, nearest wins."""
+    import itertools
+    q, L = C.shape
+    best, best_d = None, np.inf
+    for k in range(0, min(q, L) + 1):
+        for A in itertools.combinations(range(L), k):
+            t = np.array(t_star, dtype=np.float64)
+            if k:
+                M = C[:, list(A)]
+                if np.linalg.matrix_rank(M) < k:
+                    continue
+                t = t - M @ np.linalg.solve(M.T @ M, M.T @ t - b[list(A)])
+            if np.all(C.T @ t - b >= -1e-10 * (1 + np.abs(b))):
+                d = float(np.sum((t - t_star) ** 2))
+                if d < best_d:
+                    best, best_d = t, d
+    return best
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_gauge_projection_against_enumeration(seed):
+    rng = np.random.default_rng(100 + seed)
+    L = int(rng.integers(2, 9))
+    q = int(rng.integers(1, L))
+    C = np.linalg.qr(rng.standard_normal((L, q)))[0].T
+    lam = [rng.uniform(0.0, 2.0, 4) + 1e-3 for _ in range(L)]
+    eps = [1e-3] * L
+    for l in rng.choice(L, size=int(rng.integers(0, 3)), replace=False):
+        lam[l][0] = eps[l]                                  # an axis already at its bound
+    t_star = rng.standard_normal(q) * 10.0 ** rng.uniform(-2, 2)
+    b = np.array(eps) - np.array([x.min() for x in lam])
+    t = S.nearest_feasible_shift(t_star, list(C), lam, eps)
+    ref = _projection_by_enumeration(t_star, C, b)
+    np.testing.assert_allclose(t, ref, atol=1e-10 * (1 + np.abs(t_star).max()))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_nearest_feasible_shift_is_the_qp_solution(seed):
+    """The gauge rule's projection against a general constrained optimiser, up
+    to the many-axis shape of a shared frame axis with 20 row/column pairs."""
+    from scipy.optimize import LinearConstraint, minimize
+    rng = np.random.default_rng(seed)
+    L = int(rng.integers(2, 7)) if seed < 4 else 41
+    q = int(rng.integers(1, L)) if seed < 4 else 21
+    C = np.linalg.qr(rng.standard_normal((L, q)))[0].T            # q x L
+    lam = [rng.uniform(0.1, 2.0, 5) for _ in range(L)]
+    eps = [1e-3] * L
+    t_star = rng.standard_normal(q) * 3.0
+    t = S.nearest_feasible_shift(t_star, list(C), lam, eps)
+    b = np.array(eps) - np.array([x.min() for x in lam])
+    res = minimize(lambda x: np.sum((x - t_star) ** 2), np.zeros(q), jac=lambda x: 2 * (x - t_star),
+                   hess=lambda x: 2 * np.eye(q), constraints=[LinearConstraint(C.T, b, np.inf)],
+                   method="trust-constr", options={"gtol": 1e-12, "xtol": 1e-14, "maxiter": 5000})
+    assert np.all(C.T @ t - b >= -1e-12)
+    assert np.all(C.T @ res.x - b >= -1e-8)
+    # strictly convex: a feasible point no worse than the reference is the optimum
+    assert np.sum((t - t_star) ** 2) <= np.sum((res.x - t_star) ** 2) + 1e-9
+    np.testing.assert_allclose(t, res.x, atol=1e-4)
+    # KKT certificate: t - t_star = sum over active constraints of mu_l C_l, mu >= 0
+    from scipy.optimize import nnls
+    slack = C.T @ t - b
+    A = np.flatnonzero(slack <= 1e-10 * (1 + np.abs(b)))
+    if A.size == 0:
+        np.testing.assert_allclose(t, t_star, atol=1e-14)
+    else:
+        mu, rnorm = nnls(C[:, A], t - t_star)
+        assert rnorm <= 1e-10 * (1 + np.linalg.norm(t_star))
+
+
+@pytest.mark.parametrize("shape,mods", [((6, 5, 4), [(0, 1, 2)]), ((5, 4, 3, 3), [(0, 1, 2, 3)]),
+                                        ((6, 5, 4), [(0, 1, 2), (0, 2)])])
+def test_minimum_matches_a_general_bounded_optimiser(shape, mods):
+    """Balanced tensor spectra (the start's gauge leaves the box): the solve's NLL
+    is the minimum L-BFGS-B finds over the same box, the solution is in the box,
+    and its tuple sums are gauge-free (the same from a perturbed warm start)."""
+    from scipy.optimize import minimize
+    E = _spectra(shape, 2, 7)
+    if len(mods) > 1:                       # a second modality over axes 0 and 2
+        E = [E[0], E[1], E[2]]
+    prob = T.TensorProblem(E, mods)
+    res = T.solve_eigs(prob)
+    assert res.converged and res.kkt <= 1e-12
+    assert all(np.all(l >= e) for l, e in zip(res.lam, prob.eps))
+    off = np.concatenate([[0], np.cumsum(prob.ranks)])
+    split = lambda x: [x[off[l]:off[l + 1]] for l in range(prob.n_axes)]
+    f = lambda x: T.nll(split(x), prob)
+    gfun = lambda x: np.concatenate(T.grad(split(x), prob))
+    x0 = np.concatenate(T.cold_start(prob))
+    bounds = [(e, None) for l, e in enumerate(prob.eps) for _ in range(prob.ranks[l])]
+    ref = minimize(f, x0, jac=gfun, bounds=bounds, method="L-BFGS-B",
+                   options={"ftol": 1e-16, "gtol": 1e-14, "maxiter": 50000, "maxcor": 50})
+    f_ours = T.nll(res.lam, prob)
+    assert f_ours <= ref.fun + 1e-9 * abs(ref.fun)
+    assert abs(f_ours - ref.fun) <= 1e-7 * abs(ref.fun)
+    rng = np.random.default_rng(1)
+    for m in mods:
+        s_ref = T._sums(res.lam, m)
+        s_lb = T._sums(split(ref.x), m)
+        np.testing.assert_allclose(s_lb, s_ref, rtol=2e-3)
+
+
+def test_gauge_is_the_start_when_feasible_and_a_bound_otherwise():
+    """Equal rank-one spectra: the start's gauge is inside the box and is kept
+    exactly.  Balanced tensor spectra where it is not: the result's gauge is the
+    nearest feasible one, so some axis' smallest eigenvalue sits at its bound."""
+    E = _spectra((20, 32, 32), 4, 1)
+    prob = T.TensorProblem(E, [(0, 1, 2)])
+    res = T.solve_eigs(prob)
+    assert res.converged
+    flats = T.flat_directions(prob)
+    assert len(flats) == 2
+    target = T.cold_start(prob)
+    gap = [sum(c[l] * (target[l].sum() - res.lam[l].sum()) for l in range(3)) for c in flats]
+    if max(abs(x) for x in gap) > 1e-9 * sum(t.sum() for t in target):
+        assert any(abs(l.min() - e) <= 1e-12 * l.max() for l, e in zip(res.lam, prob.eps))
