@@ -169,6 +169,34 @@ def stages(g, n, p, r, workers, multimodal=True):
         out["shared_cells"] = shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, workers)
     del rpd, cd, vd
     torch.cuda.empty_cache()
+    out["tensor_solve"] = tensor_solve(g)
+    return out
+
+
+def tensor_solve(g):
+    """The eigenvalue solve at the shape of the paper's COIL-20 run: 20
+    modalities (frame, row_i, col_i) of 72 frames x 128 x 128 sharing the frame
+    axis (41 axes), with 10 and with all principal components per axis."""
+    import numpy as np
+    import torch
+
+    from tests._tensor_inputs import coil_like_spectra
+    t0 = time.perf_counter()
+    E, mods = coil_like_spectra(seed=1)
+    out = {"input": "Gram spectra of 20 synthetic rotating-object videos, 72 x 128 x 128, seed 1",
+           "axes": len(E), "modalities": len(mods)}
+    log(f"stages: tensor spectra in {time.perf_counter() - t0:.1f} s")
+    for label, r in (("top10", 10), ("all", None)):
+        Ed = [torch.from_numpy(np.ascontiguousarray(e[:r] if r else e)).cuda() for e in E]
+        g.solve_eigs_tensor(Ed, mods)                     # warm-up (workspace, library handles)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sol = g.solve_eigs_tensor(Ed, mods)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        out[label] = {"ms": wall * 1e3, "unknowns": int(sum(e.numel() for e in Ed)),
+                      **{k: sol.info[k] for k in ("iterations", "kkt", "n_flat")}}
+        log(f"stages: tensor solve ({label}) {wall * 1e3:.1f} ms, {sol.info['iterations']} iterations")
     return out
 
 

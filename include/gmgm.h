@@ -375,6 +375,39 @@ gmgm_status gmgm_solve_eigs(gmgm_ctx_t ctx, int32_t n_axes, const int64_t* ranks
                             int32_t max_iter, double* const* lambda_out, gmgm_solve_info* info);
 
 /*
+ * Eigenvalue maximum-likelihood estimate for modalities of any number of axes
+ * (tensor-variate data; the model equation with the Kronecker sum of K >= 2
+ * axes, whose eigenvalues are the sums lambda_{l_1,i_1} + ... + lambda_{l_K,i_K}
+ * over all index tuples; eigenvalue-gradient Proposition; Existence lemma):
+ * minimise over lambda_l,i >= eps_l
+ *   NLL = 1/2 [ sum_l sum_i E_l,i lambda_l,i
+ *               - sum_{modalities} sum_{index tuples} log(sum of the tuple's lambdas) ].
+ * Same method, start, gauge rule, stopping rule and record as gmgm_solve_eigs;
+ * the Newton system is dense over all sum_l r_l coordinates (the Hessian
+ * couples every two axes of a modality through sums over the others), FP64,
+ * deterministic reductions.  With every modality of two axes the solution is
+ * that of gmgm_solve_eigs.
+ *
+ *   n_axes, ranks, E, eps, warm, tol, max_iter, lambda_out, info: as for
+ *                gmgm_solve_eigs.
+ *   n_mod        1 .. 64 modalities.
+ *   mod_len      host, n_mod axis counts K_t, 2 <= K_t <= n_axes.
+ *   mod_axes     host, sum_t K_t axis indices: modality t's distinct axes,
+ *                modalities one after another.  No two modalities may have the
+ *                same axis set; every axis must belong to one.
+ * Limits: sum_l r_l <= 2048 (the dense system), at most 2^40 index tuples per
+ * modality (each iteration costs about K^2 / 2 times the tuple count in FP64
+ * divisions and logarithms).  Synchronises.  Returns GMGM_E_NOCONV (outputs
+ * written, info filled) when tol is not reached; GMGM_E_DOMAIN for
+ * non-positive or non-finite E, non-finite warm starts or bad eps.
+ */
+gmgm_status gmgm_solve_eigs_tensor(gmgm_ctx_t ctx, int32_t n_axes, const int64_t* ranks,
+                                   const double* const* E, int32_t n_mod, const int32_t* mod_len,
+                                   const int32_t* mod_axes, const double* eps,
+                                   const double* const* warm, double tol, int32_t max_iter,
+                                   double* const* lambda_out, gmgm_solve_info* info);
+
+/*
  * Learned warm start of the eigenvalue MLE: a small network predicts the
  * solution from the two axes' spectra and replaces Algorithm 1's start
  * lambda^0 = 1/E (gmgm_solve_eigs then finishes from it; its result does not

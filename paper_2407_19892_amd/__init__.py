@@ -88,6 +88,11 @@ SIGNATURES = {
                                        ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(_P), ctypes.c_double, _I32, ctypes.POINTER(_P),
                                        ctypes.POINTER(SolveInfo)]),
+    "gmgm_solve_eigs_tensor": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_P), _I32,
+                                              ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_P),
+                                              ctypes.c_double, _I32, ctypes.POINTER(_P),
+                                              ctypes.POINTER(SolveInfo)]),
 }
 
 
@@ -300,6 +305,44 @@ def solve_eigs(E, modalities, eps=None, warm=None, tol: float = 1e-12, max_iter:
     c = context(E[0].device.index)
     st = load().gmgm_solve_eigs(c, L, ranks, eptr, len(modalities), mods, epsa, wptr, float(tol),
                                 int(max_iter), optr, ctypes.byref(info))
+    d = {"iterations": info.iterations, "converged": bool(info.converged), "n_flat": info.n_flat,
+         "warm_used": bool(info.warm_used),
+         "kkt": info.kkt, "n_pinned": list(info.n_pinned[:L]), "eps": list(info.eps[:L])}
+    if st == 4 and not raise_on_noconv:
+        return SolveResult(out, d)
+    _check(c, st)
+    return SolveResult(out, d)
+
+
+def solve_eigs_tensor(E, modalities, eps=None, warm=None, tol: float = 1e-12, max_iter: int = 200,
+                      raise_on_noconv: bool = True) -> SolveResult:
+    """Eigenvalue MLE for modalities of any number of axes (see
+    gmgm_solve_eigs_tensor).  E: list of FP64 device tensors (one per axis);
+    modalities: list of axis tuples (each of two or more distinct axes)."""
+    import torch
+    L = len(E)
+    for e in E:
+        if not (e.is_cuda and e.dtype == torch.float64 and e.dim() == 1 and e.is_contiguous()):
+            raise TypeError("every E must be a contiguous 1-D float64 device tensor")
+    if warm is not None:
+        if len(warm) != L:
+            raise ValueError("warm needs one tensor per axis")
+        for w, e in zip(warm, E):
+            if not (w.is_cuda and w.dtype == torch.float64 and w.is_contiguous() and w.numel() == e.numel()):
+                raise TypeError("warm tensors must be contiguous float64 device tensors shaped like E")
+    out = [torch.empty_like(e) for e in E]
+    ranks = (_I64 * L)(*[e.numel() for e in E])
+    eptr = (_P * L)(*[e.data_ptr() for e in E])
+    optr = (_P * L)(*[o.data_ptr() for o in out])
+    lens = (_I32 * len(modalities))(*[len(m) for m in modalities])
+    flat = [int(a) for m in modalities for a in m]
+    axes = (_I32 * max(1, len(flat)))(*flat)
+    epsa = (ctypes.c_double * L)(*eps) if eps is not None else None
+    wptr = (_P * L)(*[w.data_ptr() for w in warm]) if warm is not None else None
+    info = SolveInfo()
+    c = context(E[0].device.index)
+    st = load().gmgm_solve_eigs_tensor(c, L, ranks, eptr, len(modalities), lens, axes, epsa, wptr, float(tol),
+                                       int(max_iter), optr, ctypes.byref(info))
     d = {"iterations": info.iterations, "converged": bool(info.converged), "n_flat": info.n_flat,
          "warm_used": bool(info.warm_used),
          "kkt": info.kkt, "n_pinned": list(info.n_pinned[:L]), "eps": list(info.eps[:L])}

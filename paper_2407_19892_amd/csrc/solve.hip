@@ -19,6 +19,8 @@
 // 1/E.  A warm start is used when its NLL is not above that of 1/E.
 // Reductions are deterministic (fixed order, compensated).
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <cmath>
@@ -29,8 +31,10 @@
 namespace gmgm_sv {
 
 constexpr int RED_THREADS = 1024;
-constexpr int MAX_AXES = 8;
+constexpr int MAX_AXES = 8;        // pair solver; axes of one modality (tensor solver)
 constexpr int MAX_HUB = 2048;
+constexpr int MAX_TAXES = 64;      // tensor solver: axes
+constexpr int MAX_DENSE = 8192;    // tensor solver: unknowns of the dense Newton system
 
 __device__ inline void neumaier(double& s, double& c, double x) {
   const double t = s + x;
@@ -83,6 +87,104 @@ __global__ void __launch_bounds__(256) pair_sums_kernel(const double* __restrict
     if (s2) s2[i] = accumulate ? s2[i] + a2 : a2;
     if (lg) lg[i] = accumulate ? lg[i] + a3 : a3;
   }
+}
+
+// The axes of a modality other than one or two fixed ones: their eigenvalue
+// vectors and ranks, the largest rank last (it is spread over lanes).
+struct TupleAxes {
+  const double* x[MAX_AXES];
+  int r[MAX_AXES];
+  int n;
+};
+
+// Index tuple number p of the axes o.x[0 .. nl) (the first fastest): the sum of
+// their eigenvalues.
+__device__ inline double prefix_sum(const TupleAxes& o, int nl, unsigned long long p) {
+  double s = 0.0;
+  for (int u = 0; u < nl; ++u) {
+    const unsigned long long r = (unsigned long long)o.r[u];
+    s += o.x[u][p % r];
+    p /= r;
+  }
+  return s;
+}
+
+// Tuple sums of a modality of K >= 2 axes seen from one of its axes (x, nx):
+// for every i < nx, over all index tuples of the other axes (o, o.n >= 1) with
+// s = x_i + the tuple's eigenvalues,
+//   s1[i] (+)= sum 1/s and s2[i] (+)= sum s^-2 (when s1 is given),
+//   lg[i] (+)= sum log s (when lg is given).
+// One wave per i; tuples in a fixed order (the last other axis over lanes),
+// compensated sums, so results do not depend on the launch.
+__global__ void __launch_bounds__(256) tuple_sums_kernel(const double* __restrict__ x, int nx, TupleAxes o,
+                                                         double* __restrict__ s1, double* __restrict__ s2,
+                                                         double* __restrict__ lg, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nx) return;
+  const int nl = o.n - 1;
+  unsigned long long P = 1;
+  for (int u = 0; u < nl; ++u) P *= (unsigned long long)o.r[u];
+  const double* __restrict__ last = o.x[nl];
+  const int rl = o.r[nl];
+  const bool moments = s1 != nullptr;
+  double a1 = 0, c1 = 0, a2 = 0, c2 = 0, a3 = 0, c3 = 0;
+  for (unsigned long long p = 0; p < P; ++p) {
+    const double base = x[i] + prefix_sum(o, nl, p);
+    for (int j = lane; j < rl; j += 64) {
+      const double s = base + last[j];
+      if (moments) {
+        const double r = 1.0 / s;
+        neumaier(a1, c1, r);
+        neumaier(a2, c2, r * r);
+      }
+      if (lg) neumaier(a3, c3, log(s));
+    }
+  }
+  if (moments) {
+    a1 = wave_sum(a1) + wave_sum(c1);
+    a2 = wave_sum(a2) + wave_sum(c2);
+  }
+  if (lg) a3 = wave_sum(a3) + wave_sum(c3);
+  if (lane == 0) {
+    if (moments) {
+      s1[i] = accumulate ? s1[i] + a1 : a1;
+      s2[i] = accumulate ? s2[i] + a2 : a2;
+    }
+    if (lg) lg[i] = accumulate ? lg[i] + a3 : a3;
+  }
+}
+
+// Hessian cross block of two axes A (xa, rows at offset offa) and B (xb,
+// columns at offb) of one modality: C[i][j] = sum over the index tuples of the
+// modality's other axes (o, possibly none) of 1/2 s^-2, s = xa_i + xb_j + the
+// tuple's eigenvalues; S[A][B] += C and S[B][A] += C^T.  One thread per (i, j),
+// tuples in a fixed order.
+__global__ void __launch_bounds__(256) tuple_cross_kernel(const double* __restrict__ xa, int na, int offa,
+                                                          const double* __restrict__ xb, int nb, int offb,
+                                                          TupleAxes o, double* __restrict__ S, int ldS) {
+  const int i = blockIdx.y * 16 + (threadIdx.x >> 4), j = blockIdx.x * 16 + (threadIdx.x & 15);
+  if (i >= na || j >= nb) return;
+  const double base0 = xa[i] + xb[j];
+  double acc = 0.0, cc = 0.0;
+  if (o.n == 0) {
+    acc = 0.5 / (base0 * base0);
+  } else {
+    const int nl = o.n - 1;
+    unsigned long long P = 1;
+    for (int u = 0; u < nl; ++u) P *= (unsigned long long)o.r[u];
+    const double* __restrict__ last = o.x[nl];
+    for (unsigned long long p = 0; p < P; ++p) {
+      const double base = base0 + prefix_sum(o, nl, p);
+      for (int k = 0; k < o.r[nl]; ++k) {
+        const double s = base + last[k];
+        neumaier(acc, cc, 0.5 / (s * s));
+      }
+    }
+    acc += cc;
+  }
+  S[(size_t)(offa + i) * ldS + offb + j] += acc;
+  S[(size_t)(offb + j) * ldS + offa + i] += acc;
 }
 
 // g = (E - s1)/2, h = s2/2, the active set and each coordinate's KKT term:
@@ -289,6 +391,23 @@ __global__ void __launch_bounds__(RED_THREADS) max_kernel(const double* __restri
   }
 }
 
+// *out = min_i a[i]  (one workgroup)
+__global__ void __launch_bounds__(RED_THREADS) min_kernel(const double* __restrict__ a, int n,
+                                                          double* __restrict__ out) {
+  __shared__ double red[RED_THREADS / 64];
+  double m = INFINITY;
+  for (int i = threadIdx.x; i < n; i += RED_THREADS) m = fmin(m, a[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < RED_THREADS / 64; ++w) r = fmin(r, red[w]);
+    *out = r;
+  }
+}
+
 // Trial point t = max(x + alpha d, floor) of one axis: an active coordinate may
 // reach its bound, a free one may shrink by at most STEP_SHRINK per iteration (a
 // coupled Newton step can overshoot far below the optimum, and recovery from
@@ -381,13 +500,14 @@ std::vector<int> hub_axes(const std::vector<Axis>& ax, const std::vector<std::pa
   return best;
 }
 
-// Axis shifts c (c_a + c_b = 0 for every modality) along which the NLL slope
-// 1/2 sum_l c_l tr_l vanishes; orthonormal in the metric sum_l r_l c_l c'_l.
+// Axis shifts c (sum of c over every modality's axes = 0) along which the NLL
+// slope 1/2 sum_l c_l tr_l vanishes; orthonormal in the metric sum_l r_l c_l c'_l.
 std::vector<std::vector<double>> flat_directions(const std::vector<Axis>& ax,
-                                                 const std::vector<std::pair<int, int>>& mods) {
+                                                 const std::vector<std::vector<int>>& mods) {
   const int L = (int)ax.size();
   std::vector<std::vector<double>> M(mods.size(), std::vector<double>(L, 0.0));
-  for (size_t t = 0; t < mods.size(); ++t) M[t][mods[t].first] = M[t][mods[t].second] = 1.0;
+  for (size_t t = 0; t < mods.size(); ++t)
+    for (int a : mods[t]) M[t][a] = 1.0;
   // reduced row echelon form of the incidence matrix; its null space spans the shifts
   std::vector<int> pivcol;
   int row = 0;
@@ -438,14 +558,128 @@ std::vector<std::vector<double>> flat_directions(const std::vector<Axis>& ax,
   return flats;
 }
 
-struct Solver {
+// The gauge rule inside the box.  A move by sum_q t_q c_q along the flat
+// directions (orthonormal in the gauge metric) changes the q-th gauge value by
+// t_q and leaves every tuple sum, hence the NLL and its gradient, unchanged; it
+// keeps axis l in the box while mins[l] + u_l >= eps_l, u_l = sum_q t_q c_q,l.
+// Returns the t nearest to t_star under these constraints by the primal
+// active-set method for strictly convex quadratic programs (Nocedal and Wright,
+// Numerical Optimization, Algorithm 16.3), started at the feasible t = 0 with
+// no working constraints.  Every iterate is feasible.
+std::vector<double> nearest_feasible_shift(const std::vector<double>& t_star,
+                                           const std::vector<std::vector<double>>& flats,
+                                           const std::vector<Axis>& ax, const double* mins) {
+  const int q = (int)flats.size(), L = (int)ax.size();
+  std::vector<double> b(L), t(q, 0.0);
+  for (int l = 0; l < L; ++l) b[l] = ax[l].eps - mins[l];
+  double tnorm = 0;
+  for (double x : t_star) tnorm += x * x;
+  tnorm = std::sqrt(tnorm);
+  auto normal_dot = [&](int l, const std::vector<double>& v) {
+    double s = 0;
+    for (int p = 0; p < q; ++p) s += flats[p][l] * v[p];
+    return s;
+  };
+  std::vector<int> W;
+  std::vector<char> in_w(L, 0);
+  for (int it = 0; it < 10000; ++it) {
+    std::vector<double> step(q);
+    double gn = 0;
+    for (int p = 0; p < q; ++p) {
+      step[p] = t_star[p] - t[p];
+      gn += step[p] * step[p];
+    }
+    const double tol = 1e-12 * (std::sqrt(gn) + tnorm + 1e-300);
+    const int k = (int)W.size();
+    std::vector<double> mu(k);
+    if (k > 0) {
+      // least-squares fit of the step by the working normals: (N^T N) mu = N^T step
+      std::vector<double> G(k * k);
+      for (int i = 0; i < k; ++i) {
+        for (int j = 0; j <= i; ++j) {
+          double v = 0;
+          for (int p = 0; p < q; ++p) v += flats[p][W[i]] * flats[p][W[j]];
+          G[i * k + j] = v;
+        }
+        mu[i] = normal_dot(W[i], step);
+      }
+      for (int j = 0; j < k; ++j) {   // Cholesky, lower triangle
+        double d = G[j * k + j];
+        for (int p = 0; p < j; ++p) d -= G[j * k + p] * G[j * k + p];
+        if (!(d > 0)) return t;        // dependent normals: cannot happen (a blocking normal is independent)
+        G[j * k + j] = std::sqrt(d);
+        for (int i = j + 1; i < k; ++i) {
+          double v = G[i * k + j];
+          for (int p = 0; p < j; ++p) v -= G[i * k + p] * G[j * k + p];
+          G[i * k + j] = v / G[j * k + j];
+        }
+      }
+      for (int i = 0; i < k; ++i) {
+        for (int p = 0; p < i; ++p) mu[i] -= G[i * k + p] * mu[p];
+        mu[i] /= G[i * k + i];
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        for (int p = i + 1; p < k; ++p) mu[i] -= G[p * k + i] * mu[p];
+        mu[i] /= G[i * k + i];
+      }
+      if (k == q)   // q independent normals span the space: the step is zero
+        std::fill(step.begin(), step.end(), 0.0);
+      else
+        for (int p = 0; p < q; ++p)
+          for (int i = 0; i < k; ++i) step[p] -= flats[p][W[i]] * mu[i];
+    }
+    double pn = 0;
+    for (double x : step) pn += x * x;
+    if (std::sqrt(pn) <= tol) {
+      // at the minimiser of the working set: the objective's gradient is -N mu, so
+      // a constraint with mu > 0 has a negative multiplier and leaves (compared
+      // by mu times the normal's length)
+      int drop = -1;
+      double worst = tol;
+      for (int i = 0; i < k; ++i) {
+        double len = 0;
+        for (int p = 0; p < q; ++p) len += flats[p][W[i]] * flats[p][W[i]];
+        const double size = mu[i] * std::sqrt(len);
+        if (size > worst) {
+          worst = size;
+          drop = i;
+        }
+      }
+      if (drop < 0) return t;
+      in_w[W[drop]] = 0;
+      W.erase(W.begin() + drop);
+      continue;
+    }
+    double alpha = 1.0;
+    int block = -1;
+    for (int l = 0; l < L; ++l) {
+      if (in_w[l]) continue;
+      const double rate = normal_dot(l, step);
+      if (rate < 0.0) {
+        const double a_l = std::max(0.0, normal_dot(l, t) - b[l]) / -rate;
+        if (a_l < alpha) {
+          alpha = a_l;
+          block = l;
+        }
+      }
+    }
+    for (int p = 0; p < q; ++p) t[p] += alpha * step[p];
+    if (block >= 0) {
+      W.push_back(block);
+      in_w[block] = 1;
+    }
+  }
+  return t;
+}
+
+// State shared by the pair and tensor solvers: per-axis vectors concatenated
+// (axis l at ax[l].off), the Newton system of nS unknowns, device scalars.
+struct Core {
   gmgm_ctx* c = nullptr;
   hipStream_t st = nullptr;
   int L = 0;
   std::vector<Axis> ax;
-  std::vector<std::pair<int, int>> mods;
-  std::vector<int> hub, is_hub;
-  std::vector<size_t> hoff;
+  std::vector<std::vector<int>> sets;   // each modality's axes
   size_t T = 0, nS = 0;
   double *lam, *trial, *Ec, *s1, *s2, *lg, *g, *h, *d, *acc, *kkt, *S, *rhs, *scal;
   int *act, *act_hub, *flag;
@@ -463,8 +697,8 @@ struct Solver {
       if (cdir[l] != 0.0)
         hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, v + ax[l].off,
                            (const double*)nullptr, ax[l].r, scal + q++);
-    double sums[MAX_AXES];
-    GMGM_TRY(fetch(sums, scal, q));
+    std::vector<double> sums(std::max(q, 1));
+    GMGM_TRY(fetch(sums.data(), scal, q));
     *out = 0;
     q = 0;
     for (int l = 0; l < L; ++l)
@@ -472,13 +706,37 @@ struct Solver {
     return GMGM_OK;
   }
 
-  // v += t * cdir (axis-wise constant shift)
-  void shift(double* v, const std::vector<double>& cdir, double t) {
-    for (int l = 0; l < L; ++l)
-      if (cdir[l] != 0.0)
-        hipLaunchKernelGGL(add_const_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, v + ax[l].off,
-                           ax[l].r, t * cdir[l]);
+  gmgm_status bind_workspace() {
+    void *w0, *w1;
+    GMGM_TRY(ws_get(c, WS_SOLVE0, (T * 11 + 2 * (size_t)L + 64) * sizeof(double), &w0));
+    GMGM_TRY(ws_get(c, WS_SOLVE1, nS * nS * 8 + nS * 8 + (T + nS + 64) * 4, &w1));
+    double* base = (double*)w0;
+    lam = base;
+    trial = base + T;
+    Ec = base + 2 * T;
+    s1 = base + 3 * T;
+    s2 = base + 4 * T;
+    lg = base + 5 * T;
+    g = base + 6 * T;
+    h = base + 7 * T;
+    d = base + 8 * T;
+    acc = base + 9 * T;
+    kkt = base + 10 * T;
+    scal = base + 11 * T;
+    S = (double*)w1;
+    rhs = S + nS * nS;
+    act = (int*)(rhs + nS);
+    act_hub = act + T;
+    flag = act_hub + nS;
+    return GMGM_OK;
   }
+};
+
+// Modalities of two axes: Newton system by the Schur complement on the hub axes.
+struct Solver : Core {
+  std::vector<std::pair<int, int>> mods;
+  std::vector<int> hub, is_hub;
+  std::vector<size_t> hoff;
 
   // NLL(x) = 1/2 (sum E x - sum log); each modality's log terms counted once.
   gmgm_status nll(const double* x, double* out) {
@@ -579,87 +837,117 @@ struct Solver {
   }
 };
 
-}  // namespace gmgm_sv
+// Modalities of any number of axes: the Newton system over all coordinates, dense.
+struct TensorSolver : Core {
+  // The axes of modality m other than `skip_a` and `skip_b`, the largest rank last.
+  TupleAxes others(const std::vector<int>& m, int skip_a, int skip_b, const double* x) const {
+    TupleAxes o{};
+    for (int a : m)
+      if (a != skip_a && a != skip_b) {
+        o.x[o.n] = x + ax[a].off;
+        o.r[o.n] = ax[a].r;
+        o.n++;
+      }
+    int big = 0;
+    for (int u = 1; u < o.n; ++u)
+      if (o.r[u] > o.r[big]) big = u;
+    if (o.n > 0) {
+      std::swap(o.x[big], o.x[o.n - 1]);
+      std::swap(o.r[big], o.r[o.n - 1]);
+    }
+    return o;
+  }
 
-using namespace gmgm_sv;
+  // NLL(x) = 1/2 (sum E x - sum log); each modality's log terms counted once (from its first axis).
+  gmgm_status nll(const double* x, double* out) {
+    for (int l = 0; l < L; ++l) {
+      int first = 1;
+      for (auto& m : sets)
+        if (m[0] == l) {
+          hipLaunchKernelGGL(tuple_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off,
+                             ax[l].r, others(m, l, -1, x), (double*)nullptr, (double*)nullptr,
+                             lg + ax[l].off, first ? 0 : 1);
+          first = 0;
+        }
+      if (first) GMGM_HIP(c, hipMemsetAsync(lg + ax[l].off, 0, ax[l].r * sizeof(double), st));
+    }
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, scal);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, lg, (const double*)nullptr,
+                       (int)T, scal + 1);
+    double v[2];
+    GMGM_TRY(fetch(v, scal, 2));
+    *out = 0.5 * (v[0] - v[1]);
+    return GMGM_OK;
+  }
 
-extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64_t* ranks,
-                                       const double* const* E, int32_t n_mod,
-                                       const int32_t* modalities, const double* eps,
-                                       const double* const* warm, double tol, int32_t max_iter,
-                                       double* const* lambda_out, gmgm_solve_info* info) {
-  GMGM_CHECK_CTX(c);
-  if (n_axes < 2 || n_axes > MAX_AXES) return set_err(c, GMGM_E_ARG, "n_axes must be in [2, 8]");
-  if (n_mod < 1 || n_mod > n_axes * (n_axes - 1) / 2)
-    return set_err(c, GMGM_E_ARG, "n_mod must be in [1, n_axes (n_axes - 1) / 2]");
-  if (!ranks || !E || !modalities || !lambda_out) return set_err(c, GMGM_E_ARG, "null pointer argument");
-  if (!(tol > 0) || max_iter < 0) return set_err(c, GMGM_E_ARG, "need tol > 0 and max_iter >= 0");
-  Solver sv;
-  sv.c = c;
-  sv.st = c->stream;
-  sv.L = n_axes;
-  sv.ax.resize(n_axes);
-  for (int l = 0; l < n_axes; ++l) {
-    if (ranks[l] < 1 || ranks[l] > (1 << 26))
-      return set_err(c, GMGM_E_SHAPE, "axis %d: rank %lld outside [1, 2^26]", l, (long long)ranks[l]);
-    if (!E[l] || !lambda_out[l] || (warm && !warm[l]))
-      return set_err(c, GMGM_E_ARG, "axis %d: null pointer", l);
-    if (eps && !(eps[l] > 0 && std::isfinite(eps[l])))
-      return set_err(c, GMGM_E_DOMAIN, "axis %d: eps must be positive and finite", l);
-    sv.ax[l].r = (int)ranks[l];
-    sv.ax[l].off = sv.T;
-    sv.T += sv.ax[l].r;
+  // g, h, the active set and the KKT residual at x.
+  gmgm_status gradient(const double* x, double* kres) {
+    for (int l = 0; l < L; ++l) {
+      int first = 1;
+      for (auto& m : sets) {
+        if (std::find(m.begin(), m.end(), l) == m.end()) continue;
+        hipLaunchKernelGGL(tuple_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off,
+                           ax[l].r, others(m, l, -1, x), s1 + ax[l].off, s2 + ax[l].off, (double*)nullptr,
+                           first ? 0 : 1);
+        first = 0;
+      }
+      hipLaunchKernelGGL(assemble_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, Ec + ax[l].off,
+                         x + ax[l].off, s1 + ax[l].off, s2 + ax[l].off, ax[l].eps, ax[l].r,
+                         g + ax[l].off, h + ax[l].off, act + ax[l].off, kkt + ax[l].off);
+    }
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(RED_THREADS), 0, st, kkt, (int)T, scal);
+    return fetch(kres, scal, 1);
   }
-  if (sv.T > (size_t)1 << 28) return set_err(c, GMGM_E_SHAPE, "total rank too large");
-  std::vector<int> used(n_axes, 0);
-  for (int t = 0; t < n_mod; ++t) {
-    const int a = modalities[2 * t], b = modalities[2 * t + 1];
-    if (a < 0 || b < 0 || a >= n_axes || b >= n_axes || a == b)
-      return set_err(c, GMGM_E_ARG, "modality %d joins invalid axes (%d, %d)", t, a, b);
-    for (auto& m : sv.mods)
-      if ((m.first == a && m.second == b) || (m.first == b && m.second == a))
-        return set_err(c, GMGM_E_ARG, "modality %d repeats the axis pair (%d, %d)", t, a, b);
-    sv.mods.push_back({a, b});
-    used[a] = used[b] = 1;
+
+  // Damped projected-Newton direction d at lam (g, h and act current): the free
+  // block of the Hessian with its diagonal times 1 + rho, factored densely;
+  // -g/h on active coordinates.
+  gmgm_status direction(double rho) {
+    const double damp = 1.0 + rho;
+    GMGM_HIP(c, hipMemsetAsync(S, 0, nS * nS * sizeof(double), st));
+    for (int l = 0; l < L; ++l)
+      hipLaunchKernelGGL(schur_diag_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, h + ax[l].off,
+                         g + ax[l].off, act + ax[l].off, ax[l].r, (int)ax[l].off, damp, S, (int)nS, rhs,
+                         act_hub);
+    for (auto& m : sets)
+      for (size_t t = 0; t < m.size(); ++t)
+        for (size_t t2 = t + 1; t2 < m.size(); ++t2) {
+          const int a = m[t], b = m[t2];
+          hipLaunchKernelGGL(tuple_cross_kernel, dim3(nblk(ax[b].r, 16), nblk(ax[a].r, 16)), dim3(256), 0,
+                             st, lam + ax[a].off, ax[a].r, (int)ax[a].off, lam + ax[b].off, ax[b].r,
+                             (int)ax[b].off, others(m, a, b, lam), S, (int)nS);
+        }
+    hipLaunchKernelGGL(schur_pin_kernel, dim3(nblk(nS), (unsigned)nS), dim3(256), 0, st, act_hub,
+                       (int)nS, S, rhs);
+    // S is symmetric, so its row-major storage is also the column-major matrix
+    void* hv;
+    GMGM_TRY(blas_handle(c, &hv));
+    rocblas_handle bh = (rocblas_handle)hv;
+    if (rocsolver_dpotrf(bh, rocblas_fill_lower, (rocblas_int)nS, S, (rocblas_int)nS, flag) !=
+            rocblas_status_success ||
+        rocsolver_dpotrs(bh, rocblas_fill_lower, (rocblas_int)nS, 1, S, (rocblas_int)nS, rhs, (rocblas_int)nS) !=
+            rocblas_status_success)
+      return set_err(c, GMGM_E_HIP, "rocsolver Cholesky factorisation or solve failed");
+    for (int l = 0; l < L; ++l)
+      hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, rhs + ax[l].off,
+                         g + ax[l].off, h + ax[l].off, act + ax[l].off, ax[l].r, d + ax[l].off);
+    int bad = 0;
+    GMGM_HIP(c, hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    GMGM_HIP(c, hipStreamSynchronize(st));
+    if (bad) return set_err(c, GMGM_E_NOCONV, "Newton system is not positive definite");
+    return GMGM_OK;
   }
-  for (int l = 0; l < n_axes; ++l)
-    if (!used[l]) return set_err(c, GMGM_E_ARG, "axis %d belongs to no modality", l);
-  sv.hub = hub_axes(sv.ax, sv.mods);
-  sv.is_hub.assign(n_axes, 0);
-  sv.hoff.assign(n_axes, 0);
-  for (int l : sv.hub) {
-    sv.is_hub[l] = 1;
-    sv.hoff[l] = sv.nS;
-    sv.nS += sv.ax[l].r;
-  }
-  if (sv.nS > (size_t)MAX_HUB)
-    return set_err(c, GMGM_E_SHAPE, "the Schur system has %zu unknowns (at most %d)", sv.nS, MAX_HUB);
-  GMGM_HIP(c, hipSetDevice(c->device));
+};
+
+// Start point, domain checks, bounds, the Newton iteration and the gauge rule,
+// shared by both solvers (SV supplies nll, gradient and direction).
+template <class SV>
+gmgm_status drive(SV& sv, const double* const* E, const double* eps, const double* const* warm, double tol,
+                  int32_t max_iter, double* const* lambda_out, gmgm_solve_info* info) {
+  gmgm_ctx* c = sv.c;
+  const int n_axes = sv.L;
   hipStream_t st = sv.st;
-  const size_t T = sv.T, nS = sv.nS;
-
-  void *w0, *w1;
-  GMGM_TRY(ws_get(c, WS_SOLVE0, T * sizeof(double) * 11 + 64 * sizeof(double), &w0));
-  GMGM_TRY(ws_get(c, WS_SOLVE1, nS * nS * 8 + nS * 8 + (T + nS + 64) * 4, &w1));
-  double* base = (double*)w0;
-  sv.lam = base;
-  sv.trial = base + T;
-  sv.Ec = base + 2 * T;
-  sv.s1 = base + 3 * T;
-  sv.s2 = base + 4 * T;
-  sv.lg = base + 5 * T;
-  sv.g = base + 6 * T;
-  sv.h = base + 7 * T;
-  sv.d = base + 8 * T;
-  sv.acc = base + 9 * T;
-  sv.kkt = base + 10 * T;
-  sv.scal = base + 11 * T;
-  sv.S = (double*)w1;
-  sv.rhs = sv.S + nS * nS;
-  sv.act = (int*)(sv.rhs + nS);
-  sv.act_hub = sv.act + T;
-  sv.flag = sv.act_hub + nS;
-
+  const size_t T = sv.T;
   // E, the start point, domain checks, traces and largest E of each axis
   GMGM_HIP(c, hipMemsetAsync(sv.flag, 0, sizeof(int), st));
   for (int l = 0; l < n_axes; ++l) {
@@ -676,8 +964,8 @@ extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64
   }
   int bad = 0;
   GMGM_HIP(c, hipMemcpyAsync(&bad, sv.flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  double tr[2 * MAX_AXES];
-  GMGM_TRY(sv.fetch(tr, sv.scal, 2 * n_axes));
+  std::vector<double> tr(2 * n_axes);
+  GMGM_TRY(sv.fetch(tr.data(), sv.scal, 2 * n_axes));
   if (bad == 1) return set_err(c, GMGM_E_DOMAIN, "every E must be positive and finite");
   if (bad == 2) return set_err(c, GMGM_E_DOMAIN, "the warm start must be finite");
   for (int l = 0; l < n_axes; ++l) {
@@ -687,14 +975,30 @@ extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64
                        sv.ax[l].eps, sv.ax[l].r);
   }
   // the gauge of Algorithm 1's start max(1/E, eps) along each flat direction
-  const auto flats = flat_directions(sv.ax, sv.mods);
+  const auto flats = flat_directions(sv.ax, sv.sets);
   std::vector<double> target(flats.size(), 0.0);
   for (size_t q = 0; q < flats.size(); ++q) GMGM_TRY(sv.gauge_value(sv.trial, flats[q], &target[q]));
+  // back to that gauge, as near as the box allows
   auto fix_gauge = [&](double* v) -> gmgm_status {
+    if (flats.empty()) return GMGM_OK;
+    std::vector<double> t_star(flats.size());
     for (size_t q = 0; q < flats.size(); ++q) {
       double cur;
       GMGM_TRY(sv.gauge_value(v, flats[q], &cur));
-      sv.shift(v, flats[q], target[q] - cur);
+      t_star[q] = target[q] - cur;
+    }
+    for (int l = 0; l < n_axes; ++l)
+      hipLaunchKernelGGL(min_kernel, dim3(1), dim3(RED_THREADS), 0, st, v + sv.ax[l].off, sv.ax[l].r,
+                         sv.scal + l);
+    std::vector<double> mins(n_axes);
+    GMGM_TRY(sv.fetch(mins.data(), sv.scal, n_axes));
+    const std::vector<double> t = nearest_feasible_shift(t_star, flats, sv.ax, mins.data());
+    for (int l = 0; l < n_axes; ++l) {
+      double u = 0;
+      for (size_t q = 0; q < flats.size(); ++q) u += t[q] * flats[q][l];
+      if (u != 0.0)
+        hipLaunchKernelGGL(add_const_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, v + sv.ax[l].off,
+                           sv.ax[l].r, u);
     }
     return GMGM_OK;
   };
@@ -763,18 +1067,20 @@ extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64
     GMGM_HIP(c, hipMemcpyAsync(lambda_out[l], sv.lam + sv.ax[l].off, sv.ax[l].r * sizeof(double),
                                hipMemcpyDeviceToDevice, st));
   if (info) {
-    for (int l = 0; l < n_axes; ++l)
+    // the record's per-axis arrays hold the first MAX_AXES axes
+    const int nrec = std::min(n_axes, MAX_AXES);
+    for (int l = 0; l < nrec; ++l)
       hipLaunchKernelGGL(count_pinned_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.lam + sv.ax[l].off,
                          sv.ax[l].eps, sv.ax[l].r, sv.scal + 4 + l);
     double np[MAX_AXES];
-    GMGM_TRY(sv.fetch(np, sv.scal + 4, n_axes));
+    GMGM_TRY(sv.fetch(np, sv.scal + 4, nrec));
     *info = gmgm_solve_info{};
     info->iterations = it;
     info->converged = kres <= tol;
     info->n_flat = (int32_t)flats.size();
     info->warm_used = warm_used ? 1 : 0;
     info->kkt = kres;
-    for (int l = 0; l < n_axes; ++l) {
+    for (int l = 0; l < nrec; ++l) {
       info->n_pinned[l] = (int64_t)np[l];
       info->eps[l] = sv.ax[l].eps;
     }
@@ -784,4 +1090,128 @@ extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64
     return set_err(c, GMGM_E_NOCONV, "KKT residual %.3g after %d iterations%s", kres, it,
                    stalled ? " (line search stalled)" : "");
   return GMGM_OK;
+}
+
+}  // namespace gmgm_sv
+
+using namespace gmgm_sv;
+
+extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64_t* ranks,
+                                       const double* const* E, int32_t n_mod,
+                                       const int32_t* modalities, const double* eps,
+                                       const double* const* warm, double tol, int32_t max_iter,
+                                       double* const* lambda_out, gmgm_solve_info* info) {
+  GMGM_CHECK_CTX(c);
+  if (n_axes < 2 || n_axes > MAX_AXES) return set_err(c, GMGM_E_ARG, "n_axes must be in [2, 8]");
+  if (n_mod < 1 || n_mod > n_axes * (n_axes - 1) / 2)
+    return set_err(c, GMGM_E_ARG, "n_mod must be in [1, n_axes (n_axes - 1) / 2]");
+  if (!ranks || !E || !modalities || !lambda_out) return set_err(c, GMGM_E_ARG, "null pointer argument");
+  if (!(tol > 0) || max_iter < 0) return set_err(c, GMGM_E_ARG, "need tol > 0 and max_iter >= 0");
+  Solver sv;
+  sv.c = c;
+  sv.st = c->stream;
+  sv.L = n_axes;
+  sv.ax.resize(n_axes);
+  for (int l = 0; l < n_axes; ++l) {
+    if (ranks[l] < 1 || ranks[l] > (1 << 26))
+      return set_err(c, GMGM_E_SHAPE, "axis %d: rank %lld outside [1, 2^26]", l, (long long)ranks[l]);
+    if (!E[l] || !lambda_out[l] || (warm && !warm[l]))
+      return set_err(c, GMGM_E_ARG, "axis %d: null pointer", l);
+    if (eps && !(eps[l] > 0 && std::isfinite(eps[l])))
+      return set_err(c, GMGM_E_DOMAIN, "axis %d: eps must be positive and finite", l);
+    sv.ax[l].r = (int)ranks[l];
+    sv.ax[l].off = sv.T;
+    sv.T += sv.ax[l].r;
+  }
+  if (sv.T > (size_t)1 << 28) return set_err(c, GMGM_E_SHAPE, "total rank too large");
+  std::vector<int> used(n_axes, 0);
+  for (int t = 0; t < n_mod; ++t) {
+    const int a = modalities[2 * t], b = modalities[2 * t + 1];
+    if (a < 0 || b < 0 || a >= n_axes || b >= n_axes || a == b)
+      return set_err(c, GMGM_E_ARG, "modality %d joins invalid axes (%d, %d)", t, a, b);
+    for (auto& m : sv.mods)
+      if ((m.first == a && m.second == b) || (m.first == b && m.second == a))
+        return set_err(c, GMGM_E_ARG, "modality %d repeats the axis pair (%d, %d)", t, a, b);
+    sv.mods.push_back({a, b});
+    sv.sets.push_back({a, b});
+    used[a] = used[b] = 1;
+  }
+  for (int l = 0; l < n_axes; ++l)
+    if (!used[l]) return set_err(c, GMGM_E_ARG, "axis %d belongs to no modality", l);
+  sv.hub = hub_axes(sv.ax, sv.mods);
+  sv.is_hub.assign(n_axes, 0);
+  sv.hoff.assign(n_axes, 0);
+  for (int l : sv.hub) {
+    sv.is_hub[l] = 1;
+    sv.hoff[l] = sv.nS;
+    sv.nS += sv.ax[l].r;
+  }
+  if (sv.nS > (size_t)MAX_HUB)
+    return set_err(c, GMGM_E_SHAPE, "the Schur system has %zu unknowns (at most %d)", sv.nS, MAX_HUB);
+  GMGM_HIP(c, hipSetDevice(c->device));
+  GMGM_TRY(sv.bind_workspace());
+  return drive(sv, E, eps, warm, tol, max_iter, lambda_out, info);
+}
+
+extern "C" gmgm_status gmgm_solve_eigs_tensor(gmgm_ctx_t c, int32_t n_axes, const int64_t* ranks,
+                                              const double* const* E, int32_t n_mod, const int32_t* mod_len,
+                                              const int32_t* mod_axes, const double* eps,
+                                              const double* const* warm, double tol, int32_t max_iter,
+                                              double* const* lambda_out, gmgm_solve_info* info) {
+  GMGM_CHECK_CTX(c);
+  if (n_axes < 2 || n_axes > MAX_TAXES) return set_err(c, GMGM_E_ARG, "n_axes must be in [2, %d]", MAX_TAXES);
+  if (n_mod < 1 || n_mod > MAX_TAXES) return set_err(c, GMGM_E_ARG, "n_mod must be in [1, %d]", MAX_TAXES);
+  if (!ranks || !E || !mod_len || !mod_axes || !lambda_out) return set_err(c, GMGM_E_ARG, "null pointer argument");
+  if (!(tol > 0) || max_iter < 0) return set_err(c, GMGM_E_ARG, "need tol > 0 and max_iter >= 0");
+  TensorSolver sv;
+  sv.c = c;
+  sv.st = c->stream;
+  sv.L = n_axes;
+  sv.ax.resize(n_axes);
+  for (int l = 0; l < n_axes; ++l) {
+    if (ranks[l] < 1 || ranks[l] > MAX_DENSE)
+      return set_err(c, GMGM_E_SHAPE, "axis %d: rank %lld outside [1, %d]", l, (long long)ranks[l], MAX_DENSE);
+    if (!E[l] || !lambda_out[l] || (warm && !warm[l]))
+      return set_err(c, GMGM_E_ARG, "axis %d: null pointer", l);
+    if (eps && !(eps[l] > 0 && std::isfinite(eps[l])))
+      return set_err(c, GMGM_E_DOMAIN, "axis %d: eps must be positive and finite", l);
+    sv.ax[l].r = (int)ranks[l];
+    sv.ax[l].off = sv.T;
+    sv.T += sv.ax[l].r;
+  }
+  if (sv.T > (size_t)MAX_DENSE)
+    return set_err(c, GMGM_E_SHAPE, "the Newton system has %zu unknowns (at most %d)", sv.T, MAX_DENSE);
+  std::vector<int> used(n_axes, 0);
+  int pos = 0;
+  for (int t = 0; t < n_mod; ++t) {
+    const int K = mod_len[t];
+    if (K < 2 || K > std::min(n_axes, MAX_AXES))
+      return set_err(c, GMGM_E_ARG, "modality %d has %d axes (need 2 .. min(n_axes, %d))", t, K, MAX_AXES);
+    std::vector<int> m(mod_axes + pos, mod_axes + pos + K);
+    pos += K;
+    double tuples = 1.0;
+    for (int u = 0; u < K; ++u) {
+      if (m[u] < 0 || m[u] >= n_axes) return set_err(c, GMGM_E_ARG, "modality %d names axis %d", t, m[u]);
+      for (int u2 = 0; u2 < u; ++u2)
+        if (m[u2] == m[u]) return set_err(c, GMGM_E_ARG, "modality %d repeats axis %d", t, m[u]);
+      tuples *= sv.ax[m[u]].r;
+      used[m[u]] = 1;
+    }
+    if (tuples > 1099511627776.0)
+      return set_err(c, GMGM_E_SHAPE, "modality %d has %.3g index tuples (at most 2^40)", t, tuples);
+    std::vector<int> key = m;
+    std::sort(key.begin(), key.end());
+    for (auto& q : sv.sets) {
+      std::vector<int> k2 = q;
+      std::sort(k2.begin(), k2.end());
+      if (k2 == key) return set_err(c, GMGM_E_ARG, "modality %d repeats the axes of an earlier one", t);
+    }
+    sv.sets.push_back(m);
+  }
+  for (int l = 0; l < n_axes; ++l)
+    if (!used[l]) return set_err(c, GMGM_E_ARG, "axis %d belongs to no modality", l);
+  sv.nS = sv.T;
+  GMGM_HIP(c, hipSetDevice(c->device));
+  GMGM_TRY(sv.bind_workspace());
+  return drive(sv, E, eps, warm, tol, max_iter, lambda_out, info);
 }

@@ -8,6 +8,8 @@ import pytest
 from oracle import solver as S
 from oracle import solver_tensor as T
 
+from ._tensor_inputs import low_rank_tensor_spectra
+
 
 def _kron_sum(diags):
     n = int(np.prod([d.size for d in diags]))
@@ -98,24 +100,8 @@ def test_kkt_and_shared_axes_three_axis_graph():
     assert all(np.all(l >= e) for l, e in zip(res.lam, prob.eps))
 
 
-def _spectra(shape, rank, seed, noise=0.3):
-    """Gram spectra of the unfoldings of a low-rank-plus-noise tensor (all axes
-    share the trace |X|^2, so every shift direction is flat)."""
-    import oracle
-    rng = np.random.default_rng(seed)
-    fac = [rng.standard_normal((d, rank)) for d in shape]
-    X = np.zeros(shape)
-    for q in range(rank):
-        t = fac[0][:, q]
-        for f in fac[1:]:
-            t = np.multiply.outer(t, f[:, q])
-        X += t * 2.0 ** -q
-    X += noise * rng.standard_normal(shape)
-    out = []
-    for l in range(len(shape)):
-        U = np.moveaxis(X, l, 0).reshape(shape[l], -1)
-        out.append(oracle.eigh_desc(U @ U.T)[0])
-    return out
+def _spectra(shape, rank, seed):
+    return low_rank_tensor_spectra(shape, rank, seed)
 
 
 def _projection_by_enumeration(t_star, C, b):
