@@ -332,6 +332,8 @@ def main():
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timings")
     ap.add_argument("--no-multimodal", action="store_true", help="skip the shared-cell-axis stage")
     ap.add_argument("--profile-run", action="store_true", help="one step + a 1 GiB copy, no JSON")
+    ap.add_argument("--tensor-solve-only", action="store_true",
+                    help="only the tensor-variate eigenvalue solve at the COIL-20 shape (its own JSON line)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -344,6 +346,11 @@ def main():
     import torch
 
     import paper_2407_19892_amd as g
+
+    if args.tensor_solve_only:
+        g.load()
+        print(json.dumps({"tensor_solve": tensor_solve(g)}), flush=True)
+        return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     g.load()

@@ -89,102 +89,186 @@ __global__ void __launch_bounds__(256) pair_sums_kernel(const double* __restrict
   }
 }
 
-// The axes of a modality other than one or two fixed ones: their eigenvalue
-// vectors and ranks, the largest rank last (it is spread over lanes).
-struct TupleAxes {
-  const double* x[MAX_AXES];
-  int r[MAX_AXES];
-  int n;
+// ---- batched forms for the tensor solver: one launch per pass over all
+// modalities, job tables in device memory, partial sums reduced in a fixed order.
+
+// Tuple sums of one modality seen from one of its axes (own): the other axes
+// (the largest rank last) and where its r_own partial sums go.
+struct TupleJob {
+  int own;
+  int n;                      // other axes, 1 .. MAX_AXES - 1
+  int other[MAX_AXES - 1];
+  int first_wave;             // prefix over jobs of r_own
+  int part;                   // offset of its partial sums
 };
 
-// Index tuple number p of the axes o.x[0 .. nl) (the first fastest): the sum of
-// their eigenvalues.
-__device__ inline double prefix_sum(const TupleAxes& o, int nl, unsigned long long p) {
-  double s = 0.0;
-  for (int u = 0; u < nl; ++u) {
-    const unsigned long long r = (unsigned long long)o.r[u];
-    s += o.x[u][p % r];
-    p /= r;
+// Cross block of axes a < b: the sum over the modalities holding both (terms
+// [term0, term0 + nterm) of the term table, each the modality's other axes).
+struct CrossJob {
+  int a, b;
+  int first_tile, tiles_x;    // 16 x 16 tiles, prefix over jobs
+  int term0, nterm;
+};
+struct CrossTerm {
+  int n;
+  int other[MAX_AXES - 2];
+};
+
+__device__ inline int find_job_wave(const TupleJob* __restrict__ jobs, int njobs, int w) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].first_wave <= w) lo = mid;
+    else hi = mid - 1;
   }
-  return s;
+  return lo;
 }
 
-// Tuple sums of a modality of K >= 2 axes seen from one of its axes (x, nx):
-// for every i < nx, over all index tuples of the other axes (o, o.n >= 1) with
-// s = x_i + the tuple's eigenvalues,
-//   s1[i] (+)= sum 1/s and s2[i] (+)= sum s^-2 (when s1 is given),
-//   lg[i] (+)= sum log s (when lg is given).
-// One wave per i; tuples in a fixed order (the last other axis over lanes),
-// compensated sums, so results do not depend on the launch.
-__global__ void __launch_bounds__(256) tuple_sums_kernel(const double* __restrict__ x, int nx, TupleAxes o,
-                                                         double* __restrict__ s1, double* __restrict__ s2,
-                                                         double* __restrict__ lg, int accumulate) {
+// Every job's tuple sums at x (axis l at x + ax_off[l]): with logs = 0 the
+// partials p1 = sum 1/s and p2 = sum s^-2, with logs = 1 the partial plg =
+// sum log s.  One wave per (job, index of the own axis); the tuples of all
+// but the last other axis in a fixed order, the last one over the lanes, then
+// a fixed-order wave reduction of compensated sums.
+__global__ void __launch_bounds__(256) tuple_jobs_kernel(const double* __restrict__ x,
+                                                         const int* __restrict__ ax_off,
+                                                         const int* __restrict__ ax_r,
+                                                         const TupleJob* __restrict__ jobs, int njobs,
+                                                         int total_waves, int logs, double* __restrict__ p1,
+                                                         double* __restrict__ p2, double* __restrict__ plg) {
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= nx) return;
-  const int nl = o.n - 1;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= total_waves) return;
+  const TupleJob& jb = jobs[find_job_wave(jobs, njobs, w)];
+  const int i = w - jb.first_wave;
+  const int nl = jb.n - 1;
   unsigned long long P = 1;
-  for (int u = 0; u < nl; ++u) P *= (unsigned long long)o.r[u];
-  const double* __restrict__ last = o.x[nl];
-  const int rl = o.r[nl];
-  const bool moments = s1 != nullptr;
-  double a1 = 0, c1 = 0, a2 = 0, c2 = 0, a3 = 0, c3 = 0;
+  for (int u = 0; u < nl; ++u) P *= (unsigned long long)ax_r[jb.other[u]];
+  const double* __restrict__ last = x + ax_off[jb.other[nl]];
+  const int rl = ax_r[jb.other[nl]];
+  const double xi = x[ax_off[jb.own] + i];
+  double a1 = 0, c1 = 0, a2 = 0, c2 = 0;
   for (unsigned long long p = 0; p < P; ++p) {
-    const double base = x[i] + prefix_sum(o, nl, p);
+    double base = xi;
+    unsigned long long q = p;
+    for (int u = 0; u < nl; ++u) {
+      const unsigned long long r = (unsigned long long)ax_r[jb.other[u]];
+      base += x[ax_off[jb.other[u]] + (int)(q % r)];
+      q /= r;
+    }
     for (int j = lane; j < rl; j += 64) {
       const double s = base + last[j];
-      if (moments) {
-        const double r = 1.0 / s;
-        neumaier(a1, c1, r);
-        neumaier(a2, c2, r * r);
+      if (logs) {
+        neumaier(a1, c1, log(s));
+      } else {
+        const double rs = 1.0 / s;
+        neumaier(a1, c1, rs);
+        neumaier(a2, c2, rs * rs);
       }
-      if (lg) neumaier(a3, c3, log(s));
     }
   }
-  if (moments) {
-    a1 = wave_sum(a1) + wave_sum(c1);
-    a2 = wave_sum(a2) + wave_sum(c2);
-  }
-  if (lg) a3 = wave_sum(a3) + wave_sum(c3);
+  a1 = wave_sum(a1) + wave_sum(c1);
+  if (!logs) a2 = wave_sum(a2) + wave_sum(c2);
   if (lane == 0) {
-    if (moments) {
-      s1[i] = accumulate ? s1[i] + a1 : a1;
-      s2[i] = accumulate ? s2[i] + a2 : a2;
+    if (logs) {
+      plg[jb.part + i] = a1;
+    } else {
+      p1[jb.part + i] = a1;
+      p2[jb.part + i] = a2;
     }
-    if (lg) lg[i] = accumulate ? lg[i] + a3 : a3;
   }
 }
 
-// Hessian cross block of two axes A (xa, rows at offset offa) and B (xb,
-// columns at offb) of one modality: C[i][j] = sum over the index tuples of the
-// modality's other axes (o, possibly none) of 1/2 s^-2, s = xa_i + xb_j + the
-// tuple's eigenvalues; S[A][B] += C and S[B][A] += C^T.  One thread per (i, j),
-// tuples in a fixed order.
-__global__ void __launch_bounds__(256) tuple_cross_kernel(const double* __restrict__ xa, int na, int offa,
-                                                          const double* __restrict__ xb, int nb, int offb,
-                                                          TupleAxes o, double* __restrict__ S, int ldS) {
-  const int i = blockIdx.y * 16 + (threadIdx.x >> 4), j = blockIdx.x * 16 + (threadIdx.x & 15);
-  if (i >= na || j >= nb) return;
-  const double base0 = xa[i] + xb[j];
+// assemble_kernel over all coordinates: s1, s2 are the sums of the partials of
+// the coordinate's axis' jobs (axis_jobs[axis_ptr[l] ..], modality order).
+__global__ void tensor_assemble_kernel(const double* __restrict__ E, const double* __restrict__ lam,
+                                       const double* __restrict__ p1, const double* __restrict__ p2,
+                                       const int* __restrict__ axis_of, const int* __restrict__ ax_off,
+                                       const int* __restrict__ axis_ptr, const int* __restrict__ axis_jobs,
+                                       const TupleJob* __restrict__ jobs, const double* __restrict__ eps_ax,
+                                       int n, double* __restrict__ g, double* __restrict__ h,
+                                       int* __restrict__ active, double* __restrict__ kkt) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int l = axis_of[c], i = c - ax_off[l];
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = axis_ptr[l]; k < axis_ptr[l + 1]; ++k) {
+    const int part = jobs[axis_jobs[k]].part + i;
+    s1 += p1[part];
+    s2 += p2[part];
+  }
+  const double gi = 0.5 * (E[c] - s1);
+  const double hi = 0.5 * s2;
+  const double eps = eps_ax[l];
+  g[c] = gi;
+  h[c] = hi;
+  const double reach = fmin(1e-3 * lam[c], gi / hi);
+  active[c] = (lam[c] - eps <= reach) && (gi > 0.0);
+  const bool at = lam[c] <= eps * (1.0 + 1e-12);
+  kkt[c] = (at ? fmax(0.0, -gi) : fabs(gi)) / (0.5 * E[c]);
+}
+
+// Every cross block at x: S[a][b] = S[b][a]^T = sum over the job's terms of the
+// tuple sums of 1/2 s^-2 (one compensated sum over the terms and their tuples
+// in a fixed order).  One 16 x 16 tile per workgroup, one thread per entry.
+__global__ void __launch_bounds__(256) cross_jobs_kernel(const double* __restrict__ x,
+                                                         const int* __restrict__ ax_off,
+                                                         const int* __restrict__ ax_r,
+                                                         const CrossJob* __restrict__ jobs, int njobs,
+                                                         const CrossTerm* __restrict__ terms,
+                                                         double* __restrict__ S, int ldS) {
+  const int tile = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].first_tile <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const CrossJob& jb = jobs[lo];
+  const int t = tile - jb.first_tile;
+  const int i = (t / jb.tiles_x) * 16 + (threadIdx.x >> 4), j = (t % jb.tiles_x) * 16 + (threadIdx.x & 15);
+  if (i >= ax_r[jb.a] || j >= ax_r[jb.b]) return;
+  const double base0 = x[ax_off[jb.a] + i] + x[ax_off[jb.b] + j];
   double acc = 0.0, cc = 0.0;
-  if (o.n == 0) {
-    acc = 0.5 / (base0 * base0);
-  } else {
-    const int nl = o.n - 1;
+  for (int k = 0; k < jb.nterm; ++k) {
+    const CrossTerm& tm = terms[jb.term0 + k];
+    if (tm.n == 0) {
+      neumaier(acc, cc, 0.5 / (base0 * base0));
+      continue;
+    }
+    const int nl = tm.n - 1;
     unsigned long long P = 1;
-    for (int u = 0; u < nl; ++u) P *= (unsigned long long)o.r[u];
-    const double* __restrict__ last = o.x[nl];
+    for (int u = 0; u < nl; ++u) P *= (unsigned long long)ax_r[tm.other[u]];
+    const double* __restrict__ last = x + ax_off[tm.other[nl]];
+    const int rl = ax_r[tm.other[nl]];
     for (unsigned long long p = 0; p < P; ++p) {
-      const double base = base0 + prefix_sum(o, nl, p);
-      for (int k = 0; k < o.r[nl]; ++k) {
-        const double s = base + last[k];
+      double base = base0;
+      unsigned long long q = p;
+      for (int u = 0; u < nl; ++u) {
+        const unsigned long long r = (unsigned long long)ax_r[tm.other[u]];
+        base += x[ax_off[tm.other[u]] + (int)(q % r)];
+        q /= r;
+      }
+      for (int kk = 0; kk < rl; ++kk) {
+        const double s = base + last[kk];
         neumaier(acc, cc, 0.5 / (s * s));
       }
     }
-    acc += cc;
   }
-  S[(size_t)(offa + i) * ldS + offb + j] += acc;
-  S[(size_t)(offb + j) * ldS + offa + i] += acc;
+  acc += cc;
+  S[(size_t)(ax_off[jb.a] + i) * ldS + ax_off[jb.b] + j] = acc;
+  S[(size_t)(ax_off[jb.b] + j) * ldS + ax_off[jb.a] + i] = acc;
+}
+
+// Diagonal (1+rho) h, right-hand side -g and activity flags of every coordinate
+// (S's diagonal holds zeros before).
+__global__ void tensor_diag_kernel(const double* __restrict__ h, const double* __restrict__ g,
+                                   const int* __restrict__ act, int n, double damp, double* __restrict__ S,
+                                   double* __restrict__ rhs, int* __restrict__ act_hub) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  S[(size_t)c * n + c] = damp * h[c];
+  rhs[c] = -g[c];
+  act_hub[c] = act[c];
 }
 
 // g = (E - s1)/2, h = s2/2, the active set and each coordinate's KKT term:
@@ -408,18 +492,26 @@ __global__ void __launch_bounds__(RED_THREADS) min_kernel(const double* __restri
   }
 }
 
-// Trial point t = max(x + alpha d, floor) of one axis: an active coordinate may
-// reach its bound, a free one may shrink by at most STEP_SHRINK per iteration (a
-// coupled Newton step can overshoot far below the optimum, and recovery from
-// the bound doubles the value per iteration at best).
+// Trial point t = max(x + alpha d, floor) over all coordinates (axis of
+// coordinate i: axis_of[i]): an active coordinate may reach its bound, a free
+// one may shrink by at most STEP_SHRINK per iteration (a coupled Newton step can
+// overshoot far below the optimum, and recovery from the bound doubles the
+// value per iteration at best).
 constexpr double STEP_SHRINK = 64.0;
-__global__ void trial_kernel(const double* __restrict__ x, const double* __restrict__ d,
-                             const int* __restrict__ act, int n, double alpha, double eps,
-                             double* __restrict__ t) {
+__global__ void trial_all_kernel(const double* __restrict__ x, const double* __restrict__ d,
+                                 const int* __restrict__ act, const int* __restrict__ axis_of,
+                                 const double* __restrict__ eps_ax, int n, double alpha, double* __restrict__ t) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const double eps = eps_ax[axis_of[i]];
   const double fl = act[i] ? eps : fmax(eps, x[i] / STEP_SHRINK);
   t[i] = fmax(x[i] + alpha * d[i], fl);
+}
+
+__global__ void clip_all_kernel(double* __restrict__ lam, const int* __restrict__ axis_of,
+                                const double* __restrict__ eps_ax, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) lam[i] = fmax(lam[i], eps_ax[axis_of[i]]);
 }
 
 // Armijo prediction: alpha sum_free g d + sum_active g (t - x)   (one workgroup)
@@ -451,11 +543,6 @@ __global__ void init_kernel(const double* __restrict__ E, const double* __restri
   const double v = warm ? warm[i] : 1.0 / e;
   if (warm && !isfinite(v)) atomicMax(bad, 2);
   lam[i] = v;
-}
-
-__global__ void clip_kernel(double* __restrict__ lam, double eps, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) lam[i] = fmax(lam[i], eps);
 }
 
 __global__ void __launch_bounds__(RED_THREADS) count_pinned_kernel(const double* __restrict__ lam,
@@ -681,8 +768,10 @@ struct Core {
   std::vector<Axis> ax;
   std::vector<std::vector<int>> sets;   // each modality's axes
   size_t T = 0, nS = 0;
-  double *lam, *trial, *Ec, *s1, *s2, *lg, *g, *h, *d, *acc, *kkt, *S, *rhs, *scal;
-  int *act, *act_hub, *flag;
+  double *lam, *trial, *Ec, *s1, *s2, *lg, *g, *h, *d, *acc, *kkt, *S, *rhs, *scal, *eps_ax;
+  int *act, *act_hub, *flag, *axis_of, *ax_off, *ax_r;
+  std::vector<int> h_axis_of, h_off, h_r;   // host copies (alive while copies are in flight)
+  std::vector<double> h_eps;
 
   gmgm_status fetch(double* host, const double* dev, int count) {
     GMGM_HIP(c, hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -708,7 +797,8 @@ struct Core {
 
   gmgm_status bind_workspace() {
     void *w0, *w1;
-    GMGM_TRY(ws_get(c, WS_SOLVE0, (T * 11 + 2 * (size_t)L + 64) * sizeof(double), &w0));
+    const size_t nd = T * 11 + 3 * (size_t)L + 64, ni = T + 2 * (size_t)L;
+    GMGM_TRY(ws_get(c, WS_SOLVE0, nd * sizeof(double) + ni * sizeof(int), &w0));
     GMGM_TRY(ws_get(c, WS_SOLVE1, nS * nS * 8 + nS * 8 + (T + nS + 64) * 4, &w1));
     double* base = (double*)w0;
     lam = base;
@@ -722,13 +812,46 @@ struct Core {
     d = base + 8 * T;
     acc = base + 9 * T;
     kkt = base + 10 * T;
-    scal = base + 11 * T;
+    scal = base + 11 * T;                 // 2 L + 64 scalars
+    eps_ax = scal + 2 * L + 64;
+    axis_of = (int*)(base + nd);
+    ax_off = axis_of + T;
+    ax_r = ax_off + L;
+    h_axis_of.resize(T);
+    h_off.resize(L);
+    h_r.resize(L);
+    for (int l = 0; l < L; ++l) {
+      h_off[l] = (int)ax[l].off;
+      h_r[l] = ax[l].r;
+      for (int i = 0; i < ax[l].r; ++i) h_axis_of[ax[l].off + i] = l;
+    }
+    GMGM_HIP(c, hipMemcpyAsync(axis_of, h_axis_of.data(), T * sizeof(int), hipMemcpyHostToDevice, st));
+    GMGM_HIP(c, hipMemcpyAsync(ax_off, h_off.data(), L * sizeof(int), hipMemcpyHostToDevice, st));
+    GMGM_HIP(c, hipMemcpyAsync(ax_r, h_r.data(), L * sizeof(int), hipMemcpyHostToDevice, st));
     S = (double*)w1;
     rhs = S + nS * nS;
     act = (int*)(rhs + nS);
     act_hub = act + T;
     flag = act_hub + nS;
     return GMGM_OK;
+  }
+
+  // the bounds eps_l, once known, to the device
+  gmgm_status upload_eps() {
+    h_eps.resize(L);
+    for (int l = 0; l < L; ++l) h_eps[l] = ax[l].eps;
+    GMGM_HIP(c, hipMemcpyAsync(eps_ax, h_eps.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
+    return GMGM_OK;
+  }
+
+  void clip(double* v) {
+    hipLaunchKernelGGL(clip_all_kernel, dim3(nblk(T)), dim3(256), 0, st, v, axis_of, eps_ax, (int)T);
+  }
+
+  // trial = max(lam + alpha d, floor) over all coordinates
+  void trial_point(double alpha) {
+    hipLaunchKernelGGL(trial_all_kernel, dim3(nblk(T)), dim3(256), 0, st, lam, d, act, axis_of, eps_ax, (int)T,
+                       alpha, trial);
   }
 };
 
@@ -740,6 +863,15 @@ struct Solver : Core {
 
   // NLL(x) = 1/2 (sum E x - sum log); each modality's log terms counted once.
   gmgm_status nll(const double* x, double* out) {
+    GMGM_TRY(nll_launch(x));
+    double v[2];
+    GMGM_TRY(fetch(v, scal, 2));
+    *out = 0.5 * (v[0] - v[1]);
+    return GMGM_OK;
+  }
+
+  // sum E x into scal[0] and the log sum into scal[1]
+  gmgm_status nll_launch(const double* x) {
     for (int l = 0; l < L; ++l) {
       int first = 1;
       for (auto& m : mods)
@@ -754,9 +886,6 @@ struct Solver : Core {
     hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, scal);
     hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, lg, (const double*)nullptr,
                        (int)T, scal + 1);
-    double v[2];
-    GMGM_TRY(fetch(v, scal, 2));
-    *out = 0.5 * (v[0] - v[1]);
     return GMGM_OK;
   }
 
@@ -837,86 +966,169 @@ struct Solver : Core {
   }
 };
 
-// Modalities of any number of axes: the Newton system over all coordinates, dense.
+// Modalities of any number of axes: the Newton system over all coordinates,
+// dense.  Each pass over the modalities (gradient, log sums, cross blocks) is
+// one launch driven by job tables built once per solve.
 struct TensorSolver : Core {
-  // The axes of modality m other than `skip_a` and `skip_b`, the largest rank last.
-  TupleAxes others(const std::vector<int>& m, int skip_a, int skip_b, const double* x) const {
-    TupleAxes o{};
+  std::vector<TupleJob> h_grad_jobs, h_log_jobs;
+  std::vector<CrossJob> h_cross_jobs;
+  std::vector<CrossTerm> h_terms;
+  std::vector<int> h_axis_ptr, h_axis_jobs;
+  TupleJob *grad_jobs = nullptr, *log_jobs = nullptr;
+  CrossJob* cross_jobs = nullptr;
+  CrossTerm* terms = nullptr;
+  int *axis_ptr = nullptr, *axis_jobs = nullptr;
+  double *p1 = nullptr, *p2 = nullptr, *plg = nullptr;
+  int grad_waves = 0, log_waves = 0, cross_tiles = 0, log_parts = 0;
+
+  // Axes of m other than skip_a and skip_b, the largest rank last.
+  std::vector<int> others(const std::vector<int>& m, int skip_a, int skip_b) const {
+    std::vector<int> o;
     for (int a : m)
-      if (a != skip_a && a != skip_b) {
-        o.x[o.n] = x + ax[a].off;
-        o.r[o.n] = ax[a].r;
-        o.n++;
-      }
-    int big = 0;
-    for (int u = 1; u < o.n; ++u)
-      if (o.r[u] > o.r[big]) big = u;
-    if (o.n > 0) {
-      std::swap(o.x[big], o.x[o.n - 1]);
-      std::swap(o.r[big], o.r[o.n - 1]);
+      if (a != skip_a && a != skip_b) o.push_back(a);
+    if (!o.empty()) {
+      size_t big = 0;
+      for (size_t u = 1; u < o.size(); ++u)
+        if (ax[o[u]].r > ax[o[big]].r) big = u;
+      std::swap(o[big], o.back());
     }
     return o;
   }
 
-  // NLL(x) = 1/2 (sum E x - sum log); each modality's log terms counted once (from its first axis).
-  gmgm_status nll(const double* x, double* out) {
+  // Job tables and partial-sum buffers (in WS_SOLVE2).
+  gmgm_status prepare() {
+    int part = 0;
+    h_axis_ptr.assign(L + 1, 0);
+    std::vector<std::vector<int>> per_axis(L);
+    for (auto& m : sets)
+      for (int a : m) {
+        TupleJob j{};
+        j.own = a;
+        const std::vector<int> o = others(m, a, -1);
+        j.n = (int)o.size();
+        for (int u = 0; u < j.n; ++u) j.other[u] = o[u];
+        j.first_wave = grad_waves;
+        j.part = part;
+        grad_waves += ax[a].r;
+        part += ax[a].r;
+        per_axis[a].push_back((int)h_grad_jobs.size());
+        h_grad_jobs.push_back(j);
+      }
     for (int l = 0; l < L; ++l) {
-      int first = 1;
-      for (auto& m : sets)
-        if (m[0] == l) {
-          hipLaunchKernelGGL(tuple_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off,
-                             ax[l].r, others(m, l, -1, x), (double*)nullptr, (double*)nullptr,
-                             lg + ax[l].off, first ? 0 : 1);
-          first = 0;
-        }
-      if (first) GMGM_HIP(c, hipMemsetAsync(lg + ax[l].off, 0, ax[l].r * sizeof(double), st));
+      h_axis_ptr[l + 1] = h_axis_ptr[l] + (int)per_axis[l].size();
+      for (int k : per_axis[l]) h_axis_jobs.push_back(k);
     }
-    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, scal);
-    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, lg, (const double*)nullptr,
-                       (int)T, scal + 1);
+    for (auto& m : sets) {   // each modality's log terms once, from its first axis
+      TupleJob j{};
+      j.own = m[0];
+      const std::vector<int> o = others(m, m[0], -1);
+      j.n = (int)o.size();
+      for (int u = 0; u < j.n; ++u) j.other[u] = o[u];
+      j.first_wave = log_waves;
+      j.part = log_waves;
+      log_waves += ax[m[0]].r;
+      h_log_jobs.push_back(j);
+    }
+    log_parts = log_waves;
+    for (int a = 0; a < L; ++a)
+      for (int b = a + 1; b < L; ++b) {
+        CrossJob j{};
+        j.a = a;
+        j.b = b;
+        j.term0 = (int)h_terms.size();
+        for (auto& m : sets)
+          if (std::find(m.begin(), m.end(), a) != m.end() && std::find(m.begin(), m.end(), b) != m.end()) {
+            CrossTerm tm{};
+            const std::vector<int> o = others(m, a, b);
+            tm.n = (int)o.size();
+            for (int u = 0; u < tm.n; ++u) tm.other[u] = o[u];
+            h_terms.push_back(tm);
+          }
+        j.nterm = (int)h_terms.size() - j.term0;
+        if (j.nterm == 0) continue;
+        j.tiles_x = (int)nblk(ax[b].r, 16);
+        j.first_tile = cross_tiles;
+        cross_tiles += j.tiles_x * (int)nblk(ax[a].r, 16);
+        h_cross_jobs.push_back(j);
+      }
+    auto al = [](size_t bytes) { return (bytes + 255) / 256 * 256; };
+    const size_t b_gj = al(h_grad_jobs.size() * sizeof(TupleJob)), b_lj = al(h_log_jobs.size() * sizeof(TupleJob));
+    const size_t b_cj = al(h_cross_jobs.size() * sizeof(CrossJob) + 1), b_tm = al(h_terms.size() * sizeof(CrossTerm) + 1);
+    const size_t b_ap = al((L + 1) * sizeof(int)), b_aj = al(h_axis_jobs.size() * sizeof(int));
+    const size_t b_p = al((size_t)part * sizeof(double)), b_lg = al((size_t)log_parts * sizeof(double));
+    void* w2;
+    GMGM_TRY(ws_get(c, WS_SOLVE2, b_gj + b_lj + b_cj + b_tm + b_ap + b_aj + 2 * b_p + b_lg, &w2));
+    char* q = (char*)w2;
+    grad_jobs = (TupleJob*)q;
+    q += b_gj;
+    log_jobs = (TupleJob*)q;
+    q += b_lj;
+    cross_jobs = (CrossJob*)q;
+    q += b_cj;
+    terms = (CrossTerm*)q;
+    q += b_tm;
+    axis_ptr = (int*)q;
+    q += b_ap;
+    axis_jobs = (int*)q;
+    q += b_aj;
+    p1 = (double*)q;
+    q += b_p;
+    p2 = (double*)q;
+    q += b_p;
+    plg = (double*)q;
+    auto up = [&](void* dst, const void* src, size_t bytes) -> gmgm_status {
+      if (bytes) GMGM_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+      return GMGM_OK;
+    };
+    GMGM_TRY(up(grad_jobs, h_grad_jobs.data(), h_grad_jobs.size() * sizeof(TupleJob)));
+    GMGM_TRY(up(log_jobs, h_log_jobs.data(), h_log_jobs.size() * sizeof(TupleJob)));
+    GMGM_TRY(up(cross_jobs, h_cross_jobs.data(), h_cross_jobs.size() * sizeof(CrossJob)));
+    GMGM_TRY(up(terms, h_terms.data(), h_terms.size() * sizeof(CrossTerm)));
+    GMGM_TRY(up(axis_ptr, h_axis_ptr.data(), (L + 1) * sizeof(int)));
+    GMGM_TRY(up(axis_jobs, h_axis_jobs.data(), h_axis_jobs.size() * sizeof(int)));
+    return GMGM_OK;
+  }
+
+  // NLL(x) = 1/2 (sum E x - sum log)
+  gmgm_status nll(const double* x, double* out) {
+    GMGM_TRY(nll_launch(x));
     double v[2];
     GMGM_TRY(fetch(v, scal, 2));
     *out = 0.5 * (v[0] - v[1]);
     return GMGM_OK;
   }
 
+  // sum E x into scal[0] and the log sum into scal[1]
+  gmgm_status nll_launch(const double* x) {
+    hipLaunchKernelGGL(tuple_jobs_kernel, dim3(nblk(log_waves, 4)), dim3(256), 0, st, x, ax_off, ax_r, log_jobs,
+                       (int)h_log_jobs.size(), log_waves, 1, (double*)nullptr, (double*)nullptr, plg);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, scal);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, plg, (const double*)nullptr, log_parts,
+                       scal + 1);
+    return GMGM_OK;
+  }
+
   // g, h, the active set and the KKT residual at x.
   gmgm_status gradient(const double* x, double* kres) {
-    for (int l = 0; l < L; ++l) {
-      int first = 1;
-      for (auto& m : sets) {
-        if (std::find(m.begin(), m.end(), l) == m.end()) continue;
-        hipLaunchKernelGGL(tuple_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off,
-                           ax[l].r, others(m, l, -1, x), s1 + ax[l].off, s2 + ax[l].off, (double*)nullptr,
-                           first ? 0 : 1);
-        first = 0;
-      }
-      hipLaunchKernelGGL(assemble_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, Ec + ax[l].off,
-                         x + ax[l].off, s1 + ax[l].off, s2 + ax[l].off, ax[l].eps, ax[l].r,
-                         g + ax[l].off, h + ax[l].off, act + ax[l].off, kkt + ax[l].off);
-    }
+    hipLaunchKernelGGL(tuple_jobs_kernel, dim3(nblk(grad_waves, 4)), dim3(256), 0, st, x, ax_off, ax_r, grad_jobs,
+                       (int)h_grad_jobs.size(), grad_waves, 0, p1, p2, (double*)nullptr);
+    hipLaunchKernelGGL(tensor_assemble_kernel, dim3(nblk(T)), dim3(256), 0, st, Ec, x, p1, p2, axis_of, ax_off,
+                       axis_ptr, axis_jobs, grad_jobs, eps_ax, (int)T, g, h, act, kkt);
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(RED_THREADS), 0, st, kkt, (int)T, scal);
     return fetch(kres, scal, 1);
   }
 
   // Damped projected-Newton direction d at lam (g, h and act current): the free
-  // block of the Hessian with its diagonal times 1 + rho, factored densely;
-  // -g/h on active coordinates.
+  // block of the Hessian with its diagonal times 1 + rho, factored densely by
+  // rocSOLVER; -g/h on active coordinates.
   gmgm_status direction(double rho) {
     const double damp = 1.0 + rho;
     GMGM_HIP(c, hipMemsetAsync(S, 0, nS * nS * sizeof(double), st));
-    for (int l = 0; l < L; ++l)
-      hipLaunchKernelGGL(schur_diag_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, h + ax[l].off,
-                         g + ax[l].off, act + ax[l].off, ax[l].r, (int)ax[l].off, damp, S, (int)nS, rhs,
-                         act_hub);
-    for (auto& m : sets)
-      for (size_t t = 0; t < m.size(); ++t)
-        for (size_t t2 = t + 1; t2 < m.size(); ++t2) {
-          const int a = m[t], b = m[t2];
-          hipLaunchKernelGGL(tuple_cross_kernel, dim3(nblk(ax[b].r, 16), nblk(ax[a].r, 16)), dim3(256), 0,
-                             st, lam + ax[a].off, ax[a].r, (int)ax[a].off, lam + ax[b].off, ax[b].r,
-                             (int)ax[b].off, others(m, a, b, lam), S, (int)nS);
-        }
+    hipLaunchKernelGGL(tensor_diag_kernel, dim3(nblk(T)), dim3(256), 0, st, h, g, act, (int)T, damp, S, rhs,
+                       act_hub);
+    if (cross_tiles > 0)
+      hipLaunchKernelGGL(cross_jobs_kernel, dim3((unsigned)cross_tiles), dim3(256), 0, st, lam, ax_off, ax_r,
+                         cross_jobs, (int)h_cross_jobs.size(), terms, S, (int)nS);
     hipLaunchKernelGGL(schur_pin_kernel, dim3(nblk(nS), (unsigned)nS), dim3(256), 0, st, act_hub,
                        (int)nS, S, rhs);
     // S is symmetric, so its row-major storage is also the column-major matrix
@@ -928,9 +1140,7 @@ struct TensorSolver : Core {
         rocsolver_dpotrs(bh, rocblas_fill_lower, (rocblas_int)nS, 1, S, (rocblas_int)nS, rhs, (rocblas_int)nS) !=
             rocblas_status_success)
       return set_err(c, GMGM_E_HIP, "rocsolver Cholesky factorisation or solve failed");
-    for (int l = 0; l < L; ++l)
-      hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, rhs + ax[l].off,
-                         g + ax[l].off, h + ax[l].off, act + ax[l].off, ax[l].r, d + ax[l].off);
+    hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(T)), dim3(256), 0, st, rhs, g, h, act, (int)T, d);
     int bad = 0;
     GMGM_HIP(c, hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     GMGM_HIP(c, hipStreamSynchronize(st));
@@ -971,9 +1181,9 @@ gmgm_status drive(SV& sv, const double* const* E, const double* eps, const doubl
   for (int l = 0; l < n_axes; ++l) {
     sv.ax[l].trace = tr[2 * l];
     sv.ax[l].eps = eps ? eps[l] : 1e-10 / tr[2 * l + 1];
-    hipLaunchKernelGGL(clip_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.trial + sv.ax[l].off,
-                       sv.ax[l].eps, sv.ax[l].r);
   }
+  GMGM_TRY(sv.upload_eps());
+  sv.clip(sv.trial);
   // the gauge of Algorithm 1's start max(1/E, eps) along each flat direction
   const auto flats = flat_directions(sv.ax, sv.sets);
   std::vector<double> target(flats.size(), 0.0);
@@ -1003,9 +1213,7 @@ gmgm_status drive(SV& sv, const double* const* E, const double* eps, const doubl
     return GMGM_OK;
   };
   if (warm) GMGM_TRY(fix_gauge(sv.lam));
-  for (int l = 0; l < n_axes; ++l)
-    hipLaunchKernelGGL(clip_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.lam + sv.ax[l].off,
-                       sv.ax[l].eps, sv.ax[l].r);
+  sv.clip(sv.lam);
   bool warm_used = false;
   if (warm) {
     // a supplied start is used when its NLL is not above that of 1/E (held in trial)
@@ -1032,15 +1240,13 @@ gmgm_status drive(SV& sv, const double* const* E, const double* eps, const doubl
       double alpha = 1.0;
       bool accepted = false;
       for (int ls = 0; ls < 60; ++ls) {
-        for (int l = 0; l < n_axes; ++l)
-          hipLaunchKernelGGL(trial_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.lam + sv.ax[l].off,
-                             sv.d + sv.ax[l].off, sv.act + sv.ax[l].off, sv.ax[l].r, alpha, sv.ax[l].eps,
-                             sv.trial + sv.ax[l].off);
+        sv.trial_point(alpha);
         hipLaunchKernelGGL(pred_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.g, sv.d, sv.lam, sv.trial,
                            sv.act, (int)T, alpha, sv.scal + 2);
-        double pred, f1;
-        GMGM_TRY(sv.fetch(&pred, sv.scal + 2, 1));
-        GMGM_TRY(sv.nll(sv.trial, &f1));
+        GMGM_TRY(sv.nll_launch(sv.trial));
+        double v[3];
+        GMGM_TRY(sv.fetch(v, sv.scal, 3));
+        const double f1 = 0.5 * (v[0] - v[1]), pred = v[2];
         if (f1 <= f0 + 1e-4 * pred || std::fabs(pred) <= 1e-13 * (std::fabs(f0) + 1.0)) {
           accepted = true;
           break;
@@ -1057,9 +1263,7 @@ gmgm_status drive(SV& sv, const double* const* E, const double* eps, const doubl
     // back to the start's gauge along the flat directions; resume if that moved
     // the point off the tolerance (rounding of the shift, the box)
     GMGM_TRY(fix_gauge(sv.lam));
-    for (int l = 0; l < n_axes; ++l)
-      hipLaunchKernelGGL(clip_kernel, dim3(nblk(sv.ax[l].r)), dim3(256), 0, st, sv.lam + sv.ax[l].off,
-                         sv.ax[l].eps, sv.ax[l].r);
+    sv.clip(sv.lam);
     GMGM_TRY(sv.gradient(sv.lam, &kres));
     if (kres <= tol || it >= max_iter || stalled || flats.empty()) break;
   }
@@ -1213,5 +1417,6 @@ extern "C" gmgm_status gmgm_solve_eigs_tensor(gmgm_ctx_t c, int32_t n_axes, cons
   sv.nS = sv.T;
   GMGM_HIP(c, hipSetDevice(c->device));
   GMGM_TRY(sv.bind_workspace());
+  GMGM_TRY(sv.prepare());
   return drive(sv, E, eps, warm, tol, max_iter, lambda_out, info);
 }

@@ -97,6 +97,16 @@ def test_tensor_spectra(lib, shape, rank, mods):
     _check(lib, E, mods, f"tensor {shape} {mods}")
 
 
+def test_larger_dense_system(lib):
+    """580 unknowns over 5.8 million index tuples: parity and determinism."""
+    E = low_rank_tensor_spectra((300, 160, 120), 4, seed=11)
+    _check(lib, E, [(0, 1, 2)], "580 unknowns")
+    a, _ = _gpu_solve(lib, E, [(0, 1, 2)])
+    b, _ = _gpu_solve(lib, E, [(0, 1, 2)])
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
 def test_tensor_spectra_truncated_and_explicit_eps(lib):
     """Retained ranks below the axis lengths (unbalanced: no flat direction) and
     bounds given by the caller."""
