@@ -382,22 +382,26 @@ gmgm_status gmgm_solve_eigs(gmgm_ctx_t ctx, int32_t n_axes, const int64_t* ranks
  * minimise over lambda_l,i >= eps_l
  *   NLL = 1/2 [ sum_l sum_i E_l,i lambda_l,i
  *               - sum_{modalities} sum_{index tuples} log(sum of the tuple's lambdas) ].
- * Same method, start, gauge rule, stopping rule and record as gmgm_solve_eigs;
- * the Newton system is dense over all sum_l r_l coordinates (the Hessian
- * couples every two axes of a modality through sums over the others), FP64,
- * deterministic reductions.  With every modality of two axes the solution is
- * that of gmgm_solve_eigs.
+ * Same method, start, gauge rule, stopping rule and record as gmgm_solve_eigs
+ * (the record's per-axis arrays cover axes 0..7); the Newton system is held
+ * dense over all sum_l r_l coordinates (the Hessian couples every two axes of a
+ * modality through sums over the others) and solved by eliminating each
+ * modality's private axes (those in no other modality) before the shared ones,
+ * FP64, deterministic reductions.  With every modality of two axes the solution
+ * is that of gmgm_solve_eigs.
  *
- *   n_axes, ranks, E, eps, warm, tol, max_iter, lambda_out, info: as for
- *                gmgm_solve_eigs.
+ *   n_axes       2 .. 64 axes.
+ *   ranks, E, eps, warm, tol, max_iter, lambda_out, info: as for
+ *                gmgm_solve_eigs (host arrays of n_axes entries).
  *   n_mod        1 .. 64 modalities.
- *   mod_len      host, n_mod axis counts K_t, 2 <= K_t <= n_axes.
+ *   mod_len      host, n_mod axis counts K_t, 2 <= K_t <= min(n_axes, 8).
  *   mod_axes     host, sum_t K_t axis indices: modality t's distinct axes,
  *                modalities one after another.  No two modalities may have the
  *                same axis set; every axis must belong to one.
- * Limits: sum_l r_l <= 2048 (the dense system), at most 2^40 index tuples per
- * modality (each iteration costs about K^2 / 2 times the tuple count in FP64
- * divisions and logarithms).  Synchronises.  Returns GMGM_E_NOCONV (outputs
+ * Limits: sum_l r_l <= 8192 (the system is held dense: 8 (sum_l r_l)^2 bytes
+ * of workspace), at most 2^40 index tuples per modality (each iteration costs
+ * about K (K + 1) / 2 passes over the tuples in FP64 divisions, plus a pass of
+ * logarithms per line-search trial).  Synchronises.  Returns GMGM_E_NOCONV (outputs
  * written, info filled) when tol is not reached; GMGM_E_DOMAIN for
  * non-positive or non-finite E, non-finite warm starts or bad eps.
  */

@@ -967,9 +967,17 @@ struct Solver : Core {
 };
 
 // Modalities of any number of axes: the Newton system over all coordinates,
-// dense.  Each pass over the modalities (gradient, log sums, cross blocks) is
-// one launch driven by job tables built once per solve.
+// held dense and solved by block elimination of each modality's private axes.
+// Each pass over the modalities (gradient, log sums, cross blocks) is one launch
+// driven by job tables built once per solve.
 struct TensorSolver : Core {
+  // Coordinates of each modality's private axes (those in no other modality)
+  // form one contiguous group per modality; the shared axes come last, from
+  // hub_off.  The Hessian then has the block-arrow form: private groups couple
+  // only with themselves and the shared axes.
+  std::vector<std::pair<size_t, size_t>> groups;   // (offset, size)
+  size_t hub_off = 0;
+  int* ginfo = nullptr;                           // factorisation flags of the groups
   std::vector<TupleJob> h_grad_jobs, h_log_jobs;
   std::vector<CrossJob> h_cross_jobs;
   std::vector<CrossTerm> h_terms;
@@ -1056,8 +1064,9 @@ struct TensorSolver : Core {
     const size_t b_cj = al(h_cross_jobs.size() * sizeof(CrossJob) + 1), b_tm = al(h_terms.size() * sizeof(CrossTerm) + 1);
     const size_t b_ap = al((L + 1) * sizeof(int)), b_aj = al(h_axis_jobs.size() * sizeof(int));
     const size_t b_p = al((size_t)part * sizeof(double)), b_lg = al((size_t)log_parts * sizeof(double));
+    const size_t b_gi = al((groups.size() + 1) * sizeof(int));
     void* w2;
-    GMGM_TRY(ws_get(c, WS_SOLVE2, b_gj + b_lj + b_cj + b_tm + b_ap + b_aj + 2 * b_p + b_lg, &w2));
+    GMGM_TRY(ws_get(c, WS_SOLVE2, b_gj + b_lj + b_cj + b_tm + b_ap + b_aj + 2 * b_p + b_lg + b_gi, &w2));
     char* q = (char*)w2;
     grad_jobs = (TupleJob*)q;
     q += b_gj;
@@ -1076,6 +1085,8 @@ struct TensorSolver : Core {
     p2 = (double*)q;
     q += b_p;
     plg = (double*)q;
+    q += b_lg;
+    ginfo = (int*)q;
     auto up = [&](void* dst, const void* src, size_t bytes) -> gmgm_status {
       if (bytes) GMGM_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
       return GMGM_OK;
@@ -1119,8 +1130,8 @@ struct TensorSolver : Core {
   }
 
   // Damped projected-Newton direction d at lam (g, h and act current): the free
-  // block of the Hessian with its diagonal times 1 + rho, factored densely by
-  // rocSOLVER; -g/h on active coordinates.
+  // block of the Hessian with its diagonal times 1 + rho, solved by
+  // block_arrow_solve; -g/h on active coordinates.
   gmgm_status direction(double rho) {
     const double damp = 1.0 + rho;
     GMGM_HIP(c, hipMemsetAsync(S, 0, nS * nS * sizeof(double), st));
@@ -1131,20 +1142,82 @@ struct TensorSolver : Core {
                          cross_jobs, (int)h_cross_jobs.size(), terms, S, (int)nS);
     hipLaunchKernelGGL(schur_pin_kernel, dim3(nblk(nS), (unsigned)nS), dim3(256), 0, st, act_hub,
                        (int)nS, S, rhs);
-    // S is symmetric, so its row-major storage is also the column-major matrix
+    GMGM_HIP(c, hipMemsetAsync(ginfo, 0, (groups.size() + 1) * sizeof(int), st));
+    GMGM_TRY(block_arrow_solve());
+    hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(T)), dim3(256), 0, st, rhs, g, h, act, (int)T, d);
+    std::vector<int> bad(groups.size() + 1, 0);
+    GMGM_HIP(c, hipMemcpyAsync(bad.data(), ginfo, bad.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    GMGM_HIP(c, hipStreamSynchronize(st));
+    for (int b : bad)
+      if (b) return set_err(c, GMGM_E_NOCONV, "Newton system is not positive definite");
+    return GMGM_OK;
+  }
+
+  // Solves S x = rhs in place (S symmetric positive definite, block-arrow).
+  // S is symmetric, so its row-major storage is also the column-major matrix
+  // that the library routines take (leading dimension nS).  Per group g:
+  // A_g = L_g L_g^T, B_g <- L_g^-1 B_g (B_g: the group's rows of the shared
+  // columns), y_g = L_g^-1 rhs_g; then the shared block's Schur complement
+  // C - sum_g B_g^T B_g (one rank-k update: the groups are contiguous) and
+  // right-hand side rhs_h - sum_g B_g^T y_g, its Cholesky solve, y <- y - B x_h
+  // and x_g = L_g^-T y_g.  Groups of one common size go through strided-batched
+  // calls.  Flags of the factorisations: ginfo[g], ginfo[G] for the shared block.
+  gmgm_status block_arrow_solve() {
     void* hv;
     GMGM_TRY(blas_handle(c, &hv));
     rocblas_handle bh = (rocblas_handle)hv;
-    if (rocsolver_dpotrf(bh, rocblas_fill_lower, (rocblas_int)nS, S, (rocblas_int)nS, flag) !=
-            rocblas_status_success ||
-        rocsolver_dpotrs(bh, rocblas_fill_lower, (rocblas_int)nS, 1, S, (rocblas_int)nS, rhs, (rocblas_int)nS) !=
-            rocblas_status_success)
-      return set_err(c, GMGM_E_HIP, "rocsolver Cholesky factorisation or solve failed");
-    hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(T)), dim3(256), 0, st, rhs, g, h, act, (int)T, d);
-    int bad = 0;
-    GMGM_HIP(c, hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    GMGM_HIP(c, hipStreamSynchronize(st));
-    if (bad) return set_err(c, GMGM_E_NOCONV, "Newton system is not positive definite");
+    const rocblas_int ld = (rocblas_int)nS, nh = (rocblas_int)(nS - hub_off), G = (rocblas_int)groups.size();
+    const rocblas_int k = (rocblas_int)hub_off;
+    const double one = 1.0, minus = -1.0;
+    bool ok = true;
+    auto chk = [&](rocblas_status r) { ok = ok && r == rocblas_status_success; };
+    bool equal = G > 1;
+    for (auto& gp : groups) equal = equal && gp.second == groups[0].second;
+    double* Bh = S + hub_off * nS;   // column hub_off, row 0: all groups' rows of the shared columns
+    if (equal) {
+      const rocblas_int p = (rocblas_int)groups[0].second;
+      const rocblas_stride sa = (rocblas_stride)p * (ld + 1);
+      chk(rocsolver_dpotrf_strided_batched(bh, rocblas_fill_lower, p, S, ld, sa, ginfo, G));
+      if (nh > 0)
+        chk(rocblas_dtrsm_strided_batched(bh, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                                          rocblas_diagonal_non_unit, p, nh, &one, S, ld, sa, Bh, ld, p, G));
+      chk(rocblas_dtrsv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, p,
+                                        S, ld, sa, rhs, 1, p, G));
+    } else {
+      for (rocblas_int q = 0; q < G; ++q) {
+        const rocblas_int o = (rocblas_int)groups[q].first, p = (rocblas_int)groups[q].second;
+        double* A = S + (size_t)o * nS + o;
+        chk(rocsolver_dpotrf(bh, rocblas_fill_lower, p, A, ld, ginfo + q));
+        if (nh > 0)
+          chk(rocblas_dtrsm(bh, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                            rocblas_diagonal_non_unit, p, nh, &one, A, ld, Bh + o, ld));
+        chk(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, p, A, ld,
+                          rhs + o, 1));
+      }
+    }
+    if (nh > 0) {
+      double* C = S + hub_off * nS + hub_off;
+      if (k > 0) {
+        chk(rocblas_dsyrk(bh, rocblas_fill_lower, rocblas_operation_transpose, nh, k, &minus, Bh, ld, &one, C, ld));
+        chk(rocblas_dgemv(bh, rocblas_operation_transpose, k, nh, &minus, Bh, ld, rhs, 1, &one, rhs + hub_off, 1));
+      }
+      chk(rocsolver_dpotrf(bh, rocblas_fill_lower, nh, C, ld, ginfo + G));
+      chk(rocsolver_dpotrs(bh, rocblas_fill_lower, nh, 1, C, ld, rhs + hub_off, nh));
+      if (k > 0)
+        chk(rocblas_dgemv(bh, rocblas_operation_none, k, nh, &minus, Bh, ld, rhs + hub_off, 1, &one, rhs, 1));
+    }
+    if (equal) {
+      const rocblas_int p = (rocblas_int)groups[0].second;
+      chk(rocblas_dtrsv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit,
+                                        p, S, ld, (rocblas_stride)p * (ld + 1), rhs, 1, p, G));
+    } else {
+      for (rocblas_int q = 0; q < G; ++q) {
+        const rocblas_int o = (rocblas_int)groups[q].first, p = (rocblas_int)groups[q].second;
+        chk(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit, p,
+                          S + (size_t)o * nS + o, ld, rhs + o, 1));
+      }
+    }
+    if (!ok) return set_err(c, GMGM_E_HIP, "rocBLAS or rocSOLVER call failed in the Newton solve");
     return GMGM_OK;
   }
 };
@@ -1414,6 +1487,26 @@ extern "C" gmgm_status gmgm_solve_eigs_tensor(gmgm_ctx_t c, int32_t n_axes, cons
   }
   for (int l = 0; l < n_axes; ++l)
     if (!used[l]) return set_err(c, GMGM_E_ARG, "axis %d belongs to no modality", l);
+  // coordinate order: each modality's private axes together, then the shared axes
+  std::vector<int> n_of(n_axes, 0);
+  for (auto& m : sv.sets)
+    for (int a : m) n_of[a]++;
+  size_t off = 0;
+  for (auto& m : sv.sets) {
+    const size_t o = off;
+    for (int a : m)
+      if (n_of[a] == 1) {
+        sv.ax[a].off = off;
+        off += sv.ax[a].r;
+      }
+    if (off > o) sv.groups.push_back({o, off - o});
+  }
+  sv.hub_off = off;
+  for (int l = 0; l < n_axes; ++l)
+    if (n_of[l] > 1) {
+      sv.ax[l].off = off;
+      off += sv.ax[l].r;
+    }
   sv.nS = sv.T;
   GMGM_HIP(c, hipSetDevice(c->device));
   GMGM_TRY(sv.bind_workspace());
