@@ -197,32 +197,43 @@ def newton_direction(lam, g, free, prob: Problem, rho: float):
     return d
 
 
-def flat_directions(prob: Problem, rel_tol: float = 1e-12):
-    """Axis shifts c (sum over each modality's axes = 0) along which the NLL is constant."""
-    L = prob.n_axes
-    M = np.zeros((len(prob.modalities), L))
-    for t, (a, b) in enumerate(prob.modalities):
-        M[t, a] = 1.0
-        M[t, b] = 1.0
-    _, s, Vt = np.linalg.svd(M)
-    rank = int(np.sum(s > 1e-12))
-    null = Vt[rank:]
-    tr = np.array([e.sum() for e in prob.E])
-    flats = []
-    for c in null:
-        slope = 0.5 * float(c @ tr)
-        if abs(slope) <= rel_tol * 0.5 * float(np.abs(c) @ tr):
-            flats.append(c)
-    # orthonormalise in the metric <c, c'> = sum_l r_l c_l c'_l
-    r = np.array(prob.ranks, dtype=np.float64)
+def flat_shift_space(axis_sets, ranks, traces, rel_tol: float = 1e-12):
+    """Axis shifts c along which the NLL is constant: every modality's tuple sums
+    unchanged (sum of c over its axes = 0, the null space of the modality-axis
+    incidence matrix, Identifiability appendix) and the linear term unchanged
+    (slope 1/2 sum_l c_l tr_l = 0).  The null space comes from the SVD; if every
+    basis vector's slope vanishes (to rel_tol of sum_l |c_l| tr_l) the whole
+    null space is flat, else the flat shifts are its subspace orthogonal to the
+    slope vector.  Returned orthonormal in the metric <c, c'> = sum_l r_l c_l c'_l."""
+    L = len(ranks)
+    M = np.zeros((len(axis_sets), L))
+    for t, m in enumerate(axis_sets):
+        M[t, list(m)] = 1.0
+    _, sv, Vt = np.linalg.svd(M)
+    rank = int(np.sum(sv > 1e-12))
+    N = Vt[rank:].T                                        # L x d, orthonormal columns
+    if N.shape[1] == 0:
+        return []
+    tr = np.asarray(traces, dtype=np.float64)
+    slope = N.T @ tr
+    if np.any(np.abs(slope) > rel_tol * (np.abs(N).T @ tr)):
+        # the coefficient vectors orthogonal to the slope vector
+        _, _, Wt = np.linalg.svd(slope[None, :])
+        N = N @ Wt[1:].T
+    r = np.asarray(ranks, dtype=np.float64)
     out = []
-    for c in flats:
+    for c in N.T:
         for q in out:
             c = c - (np.sum(r * c * q)) * q
         nrm = math.sqrt(np.sum(r * c * c))
         if nrm > 1e-12:
             out.append(c / nrm)
     return out
+
+
+def flat_directions(prob: Problem, rel_tol: float = 1e-12):
+    """Axis shifts c (sum over each modality's axes = 0) along which the NLL is constant."""
+    return flat_shift_space(prob.modalities, prob.ranks, [e.sum() for e in prob.E], rel_tol)
 
 
 def _gauge_value(lam, c):

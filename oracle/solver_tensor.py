@@ -32,7 +32,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .solver import default_eps, nearest_feasible_shift
+from .solver import default_eps, flat_shift_space, nearest_feasible_shift
 
 STEP_SHRINK = 64.0
 
@@ -109,25 +109,9 @@ def hess_dense(lam, prob: TensorProblem):
 
 
 def flat_directions(prob: TensorProblem, rel_tol: float = 1e-12):
-    """Axis shifts c (sum over each modality's axes = 0) along which the NLL is constant."""
-    L = prob.n_axes
-    M = np.zeros((len(prob.modalities), L))
-    for t, m in enumerate(prob.modalities):
-        M[t, list(m)] = 1.0
-    _, s, Vt = np.linalg.svd(M)
-    rank = int(np.sum(s > 1e-12))
-    null = Vt[rank:]
-    tr = np.array([e.sum() for e in prob.E])
-    flats = [c for c in null if abs(0.5 * float(c @ tr)) <= rel_tol * 0.5 * float(np.abs(c) @ tr)]
-    r = np.array(prob.ranks, dtype=np.float64)
-    out = []
-    for c in flats:
-        for q in out:
-            c = c - (np.sum(r * c * q)) * q
-        nrm = math.sqrt(np.sum(r * c * c))
-        if nrm > 1e-12:
-            out.append(c / nrm)
-    return out
+    """Axis shifts c (sum over each modality's axes = 0) along which the NLL is
+    constant (oracle.solver.flat_shift_space)."""
+    return flat_shift_space(prob.modalities, prob.ranks, [e.sum() for e in prob.E], rel_tol)
 
 
 def cold_start(prob: TensorProblem):

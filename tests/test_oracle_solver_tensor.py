@@ -221,3 +221,47 @@ def test_gauge_is_the_start_when_feasible_and_a_bound_otherwise():
     gap = [sum(c[l] * (target[l].sum() - res.lam[l].sum()) for l in range(3)) for c in flats]
     if max(abs(x) for x in gap) > 1e-9 * sum(t.sum() for t in target):
         assert any(abs(l.min() - e) <= 1e-12 * l.max() for l, e in zip(res.lam, prob.eps))
+
+
+@pytest.mark.parametrize("ranks,mods,balanced_pairs,want", [
+    ((4, 3, 5), [(0, 1, 2)], False, 1),                       # one modality, K = 3, unequal traces: K - 2
+    ((4, 3, 5, 2), [(0, 1, 2, 3)], False, 2),                 # K = 4: K - 2
+    ((6, 6, 4, 5, 3), [(0, 1), (2, 3, 4)], True, 2),          # balanced pair (1) + unbalanced triple (1)
+    ((6, 6, 4, 5, 3), [(0, 1), (2, 3, 4)], False, 2),         # both unbalanced: null space 3, less 1
+    ((5, 7, 4), [(0, 1), (0, 2)], False, 0),                  # shared axis, one null direction, sloped
+    ((4, 4, 3, 3), [(0, 1), (1, 2), (2, 3), (0, 3)], False, 0),  # even cycle, sloped
+])
+def test_flat_shift_space_dimension_and_constancy(ranks, mods, balanced_pairs, want):
+    """The flat shifts: their number (by hand: the null space of the incidence
+    matrix, less one when some null shift has a slope), and the NLL is constant
+    along each of them, evaluated from its definition."""
+    rng = np.random.default_rng(sum(ranks))
+    E = [np.sort(rng.uniform(0.5, 4.0, r))[::-1].copy() for r in ranks]
+    if balanced_pairs:                                        # equal traces on the pair modality's axes
+        E[1] = E[0].copy()
+    prob = T.TensorProblem(E, mods)
+    flats = T.flat_directions(prob)
+    assert len(flats) == want
+    lam = [rng.uniform(1.0, 2.0, r) for r in ranks]
+    f0 = T.nll(lam, prob)
+    r = np.array(ranks, dtype=np.float64)
+    for i, c in enumerate(flats):
+        assert abs(np.sum(r * c * c) - 1.0) < 1e-12
+        for j in range(i):
+            assert abs(np.sum(r * c * flats[j])) < 1e-12
+        for t in (-0.3, 0.2, 0.5):
+            moved = [l + t * c[a] for a, l in enumerate(lam)]
+            assert abs(T.nll(moved, prob) - f0) <= 1e-11 * abs(f0)
+
+
+def test_flat_shift_space_does_not_depend_on_the_basis():
+    """Same axis sets listed in another order (a different SVD basis): the same
+    flat subspace (equal projectors in the gauge metric)."""
+    rng = np.random.default_rng(4)
+    ranks = (5, 4, 6, 3, 4)
+    E = [np.sort(rng.uniform(0.5, 4.0, r))[::-1].copy() for r in ranks]
+    a = T.flat_directions(T.TensorProblem(E, [(0, 1), (2, 3, 4)]))
+    b = T.flat_directions(T.TensorProblem(E, [(4, 3, 2), (1, 0)]))
+    P = lambda F: sum(np.outer(c, c) for c in F) @ np.diag(ranks)
+    assert len(a) == len(b) == 2
+    np.testing.assert_allclose(P(a), P(b), atol=1e-12)

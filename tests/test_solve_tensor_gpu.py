@@ -107,6 +107,39 @@ def test_larger_dense_system(lib):
         assert np.array_equal(x, y)
 
 
+def test_flat_combinations_across_modalities(lib):
+    """A balanced pair modality beside an unbalanced three-axis one: the null
+    space of the incidence matrix is 3-dimensional, its zero-slope part 2."""
+    rng = np.random.default_rng(0)
+    e0 = np.sort(rng.uniform(1, 5, 6))[::-1].copy()
+    E = [e0, e0.copy(), np.sort(rng.uniform(1, 5, 4))[::-1].copy(), np.sort(rng.uniform(1, 5, 5))[::-1].copy(),
+         np.sort(rng.uniform(1, 5, 3))[::-1].copy()]
+    prob, ref, lam, info = _check(lib, E, [(0, 1), (2, 3, 4)], "flat combinations")
+    assert info["n_flat"] == 2 == len(T.flat_directions(prob))
+
+
+def test_eight_axis_modality_and_sixty_four_axes(lib):
+    """The limits: one modality of 8 axes (with a pair modality beside it), and
+    64 axes in 21 modalities (frame, a_i, b_i, c_i) with private groups of
+    equal size."""
+    rng = np.random.default_rng(12)
+    E8 = low_rank_tensor_spectra((3, 2, 2, 2, 3, 2, 2, 2), 1, seed=8)
+    _check(lib, E8, [tuple(range(8)), (0, 4)], "8-axis modality")
+    E64 = [np.sort(rng.uniform(0.5, 4.0, 3))[::-1].copy() for _ in range(64)]
+    mods = [(0, 1 + 3 * i, 2 + 3 * i, 3 + 3 * i) for i in range(21)]
+    prob, ref, lam, info = _check(lib, E64, mods, "64 axes")
+    assert len(lam) == 64 and info["n_flat"] == len(T.flat_directions(prob))
+
+
+def test_private_groups_of_different_sizes(lib):
+    """Shared frame axis, private groups of 1, 2 and 2 axes with different
+    ranks (the per-group factorisation path)."""
+    E = low_rank_tensor_spectra((12, 9, 7), 3, seed=21)
+    rng = np.random.default_rng(22)
+    extra = [np.sort(rng.uniform(0.5, 30.0, r))[::-1].copy() for r in (5, 8, 6)]
+    _check(lib, E + extra, [(0, 1, 2), (0, 3), (0, 4, 5)], "groups 16 / 5 / 14")
+
+
 def test_tensor_spectra_truncated_and_explicit_eps(lib):
     """Retained ranks below the axis lengths (unbalanced: no flat direction) and
     bounds given by the caller."""
@@ -170,6 +203,9 @@ def test_errors(lib):
         with pytest.raises(lib.GmgmError) as ei:
             _gpu_solve(lib, E, mods)
         assert ei.value.status == 1, mods
+    with pytest.raises(lib.GmgmError) as ei:        # more than 64 axes
+        _gpu_solve(lib, [np.array([1.0])] * 65, [(0, l) for l in range(1, 65)])
+    assert ei.value.status == 1
     with pytest.raises(lib.GmgmError) as ei:        # more than 8 axes in one modality
         _gpu_solve(lib, [np.array([1.0])] * 9, [tuple(range(9))])
     assert ei.value.status == 1
