@@ -399,9 +399,11 @@ gmgm_status gmgm_solve_eigs(gmgm_ctx_t ctx, int32_t n_axes, const int64_t* ranks
  *                modalities one after another.  No two modalities may have the
  *                same axis set; every axis must belong to one.
  * Limits: sum_l r_l <= 8192 (the system is held dense: 8 (sum_l r_l)^2 bytes
- * of workspace), at most 2^40 index tuples per modality (each iteration costs
- * about K (K + 1) / 2 passes over the tuples in FP64 divisions, plus a pass of
- * logarithms per line-search trial).  Synchronises.  Returns GMGM_E_NOCONV (outputs
+ * of workspace); per modality at most 2^40 index tuples, the product of any
+ * K - 1 of its ranks at most 2^32 and of any K - 2 at most 2^26 (the work of
+ * one wave and of one cross-block thread); GMGM_E_SHAPE otherwise.  Each
+ * iteration costs about K (K + 1) / 2 passes over the tuples in FP64
+ * divisions, plus a pass of logarithms per line-search trial.  Synchronises.  Returns GMGM_E_NOCONV (outputs
  * written, info filled) when tol is not reached; GMGM_E_DOMAIN for
  * non-positive or non-finite E, non-finite warm starts or bad eps.
  */

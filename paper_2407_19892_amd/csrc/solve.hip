@@ -1299,6 +1299,19 @@ extern "C" gmgm_status gmgm_solve_eigs_tensor(gmgm_ctx_t c, int32_t n_axes, cons
     }
     if (tuples > 1099511627776.0)
       return set_err(c, GMGM_E_SHAPE, "modality %d has %.3g index tuples (at most 2^40)", t, tuples);
+    // bounded work per wave (the tuples of one index: the other K - 1 ranks)
+    // and per cross-block thread (the other K - 2 ranks)
+    std::vector<double> rk;
+    for (int a : m) rk.push_back((double)sv.ax[a].r);
+    std::sort(rk.begin(), rk.end());
+    double rest1 = 1.0, rest2 = 1.0;
+    for (int u = 1; u < K; ++u) rest1 *= rk[u];
+    for (int u = 2; u < K; ++u) rest2 *= rk[u];
+    if (rest1 > 4294967296.0 || rest2 > 67108864.0)
+      return set_err(c, GMGM_E_SHAPE,
+                     "modality %d: %.3g tuples per index of its smallest axis (at most 2^32) or %.3g per entry "
+                     "of a cross block (at most 2^26)",
+                     t, rest1, rest2);
     std::vector<int> key = m;
     std::sort(key.begin(), key.end());
     for (auto& q : sv.sets) {

@@ -214,6 +214,9 @@ def test_errors(lib):
     assert ei.value.status == 4
     lam, info = _gpu_solve(lib, E, [(0, 1, 2)], max_iter=1, raise_on_noconv=False)
     assert not info["converged"] and info["iterations"] == 1
+    with pytest.raises(lib.GmgmError) as ei:        # one wave's share above 2^32 tuples
+        _gpu_solve(lib, [np.ones(1)] + [np.linspace(2.0, 1.0, 2000)] * 3, [(0, 1, 2, 3)])
+    assert ei.value.status == 2
     with pytest.raises(lib.GmgmError) as ei:        # dense system too large
         big = np.linspace(2.0, 1.0, 4100)
         _gpu_solve(lib, [big, big.copy(), np.array([1.0])], [(0, 1, 2)])
