@@ -1,23 +1,30 @@
 // Eigenvalue maximum-likelihood estimate on the GPU (FP64).
 //
 // With Theorem 1's eigenvectors fixed, the model equation's negative
-// log-likelihood of modalities gamma = (a, b) in the eigenvalues is
+// log-likelihood in the eigenvalues is, for modalities gamma = (a, b),
 //   NLL = 1/2 [ sum_l sum_i E_l,i lam_l,i - sum_gamma sum_{i,j} log(lam_a,i + lam_b,j) ],
-// its gradient (eigenvalue-gradient Proposition)
+// with gradient (eigenvalue-gradient Proposition)
 //   dNLL/dlam_l,i = 1/2 ( E_l,i - sum_{partners m} sum_j 1/(lam_l,i + lam_m,j) ),
-// minimised over the Existence lemma's box lam_l,i >= eps_l.
+// and for modalities of K axes the log term sums over all index tuples of the
+// tuple's eigenvalue sum; minimised over the Existence lemma's box
+// lam_l,i >= eps_l.
 //
 // Method: projected Newton for bound constraints with a vanishing
 // Levenberg-Marquardt damping rho = min(1e-2, KKT residual) and an Armijo
 // search along the projection arc.  The host drives the iteration; every
-// arithmetic step runs in the kernels below.  The Newton system is solved by
-// a Schur complement: "hub" axes (a minimum-rank vertex cover of the modality
-// graph) stay, the other axes have diagonal Hessian blocks and are
-// eliminated; the hub system is factored by a one-workgroup Cholesky.
-// Along directions that shift whole axes with zero NLL slope (balanced
-// problems) the NLL is constant; the result is moved to the gauge of the start
-// 1/E.  A warm start is used when its NLL is not above that of 1/E.
-// Reductions are deterministic (fixed order, compensated).
+// arithmetic step runs in the kernels below (and rocBLAS/rocSOLVER for dense
+// factorisations).  Two solvers share the driver:
+//  - pairs (gmgm_solve_eigs): a Schur complement on "hub" axes (a minimum-rank
+//    vertex cover of the modality graph; the other axes have diagonal Hessian
+//    blocks and are eliminated), the hub system factored by a one-workgroup
+//    Cholesky;
+//  - any number of axes (gmgm_solve_eigs_tensor): batched tuple sums, the
+//    Newton system held dense and solved by block elimination of each
+//    modality's private axes.
+// Along axis shifts with zero NLL slope the NLL is constant; the result is
+// moved to the gauge of the start 1/E as far as the box allows.  A warm start
+// is used when its NLL is not above that of 1/E.  Reductions are deterministic
+// (fixed order, compensated).
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
