@@ -483,12 +483,23 @@ __global__ void __launch_bounds__(RED_THREADS) max_kernel(const double* __restri
   }
 }
 
-// *out = min_i a[i]  (one workgroup)
-__global__ void __launch_bounds__(RED_THREADS) min_kernel(const double* __restrict__ a, int n,
-                                                          double* __restrict__ out) {
+// Per axis l (one workgroup each): sums[l] = sum of v over the axis (the order
+// and compensation of dot_kernel) and mins[l] = its minimum.
+__global__ void __launch_bounds__(RED_THREADS) axis_stats_kernel(const double* __restrict__ v,
+                                                                 const int* __restrict__ ax_off,
+                                                                 const int* __restrict__ ax_r,
+                                                                 double* __restrict__ sums,
+                                                                 double* __restrict__ mins) {
   __shared__ double red[RED_THREADS / 64];
-  double m = INFINITY;
-  for (int i = threadIdx.x; i < n; i += RED_THREADS) m = fmin(m, a[i]);
+  const int l = blockIdx.x;
+  const double* __restrict__ a = v + ax_off[l];
+  const int n = ax_r[l];
+  double s = 0, c = 0, m = INFINITY;
+  for (int i = threadIdx.x; i < n; i += RED_THREADS) {
+    neumaier(s, c, a[i]);
+    m = fmin(m, a[i]);
+  }
+  const double t = block_sum(s + c, red);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -496,7 +507,8 @@ __global__ void __launch_bounds__(RED_THREADS) min_kernel(const double* __restri
   if (threadIdx.x == 0) {
     double r = red[0];
     for (int w = 1; w < RED_THREADS / 64; ++w) r = fmin(r, red[w]);
-    *out = r;
+    sums[l] = t;
+    mins[l] = r;
   }
 }
 
@@ -609,20 +621,22 @@ struct Core {
     return GMGM_OK;
   }
 
-  // sum_l cdir_l sum_i v_l,i
-  gmgm_status gauge_value(const double* v, const std::vector<double>& cdir, double* out) {
-    int q = 0;
-    for (int l = 0; l < L; ++l)
-      if (cdir[l] != 0.0)
-        hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, v + ax[l].off,
-                           (const double*)nullptr, ax[l].r, scal + q++);
-    std::vector<double> sums(std::max(q, 1));
-    GMGM_TRY(fetch(sums.data(), scal, q));
-    *out = 0;
-    q = 0;
-    for (int l = 0; l < L; ++l)
-      if (cdir[l] != 0.0) *out += cdir[l] * sums[q++];
+  // every axis' sum and minimum of v (one launch, one read-back)
+  gmgm_status axis_stats(const double* v, std::vector<double>& sums, std::vector<double>& mins) {
+    hipLaunchKernelGGL(axis_stats_kernel, dim3(L), dim3(RED_THREADS), 0, st, v, ax_off, ax_r, scal, scal + L);
+    std::vector<double> both(2 * L);
+    GMGM_TRY(fetch(both.data(), scal, 2 * L));
+    sums.assign(both.begin(), both.begin() + L);
+    mins.assign(both.begin() + L, both.end());
     return GMGM_OK;
+  }
+
+  // sum_l cdir_l sums_l (axes with cdir_l = 0 skipped)
+  static double gauge_value(const std::vector<double>& sums, const std::vector<double>& cdir) {
+    double out = 0;
+    for (size_t l = 0; l < sums.size(); ++l)
+      if (cdir[l] != 0.0) out += cdir[l] * sums[l];
+    return out;
   }
 
   gmgm_status bind_workspace() {
@@ -1089,22 +1103,17 @@ gmgm_status drive(SV& sv, const double* const* E, const double* eps, const doubl
   sv.clip(sv.trial);
   // the gauge of Algorithm 1's start max(1/E, eps) along each flat direction
   const auto flats = flat_directions(sv.ax, sv.sets);
-  std::vector<double> target(flats.size(), 0.0);
-  for (size_t q = 0; q < flats.size(); ++q) GMGM_TRY(sv.gauge_value(sv.trial, flats[q], &target[q]));
+  std::vector<double> target(flats.size(), 0.0), sums, mins;
+  if (!flats.empty()) {
+    GMGM_TRY(sv.axis_stats(sv.trial, sums, mins));
+    for (size_t q = 0; q < flats.size(); ++q) target[q] = SV::gauge_value(sums, flats[q]);
+  }
   // back to that gauge, as near as the box allows
   auto fix_gauge = [&](double* v) -> gmgm_status {
     if (flats.empty()) return GMGM_OK;
+    GMGM_TRY(sv.axis_stats(v, sums, mins));
     std::vector<double> t_star(flats.size());
-    for (size_t q = 0; q < flats.size(); ++q) {
-      double cur;
-      GMGM_TRY(sv.gauge_value(v, flats[q], &cur));
-      t_star[q] = target[q] - cur;
-    }
-    for (int l = 0; l < n_axes; ++l)
-      hipLaunchKernelGGL(min_kernel, dim3(1), dim3(RED_THREADS), 0, st, v + sv.ax[l].off, sv.ax[l].r,
-                         sv.scal + l);
-    std::vector<double> mins(n_axes);
-    GMGM_TRY(sv.fetch(mins.data(), sv.scal, n_axes));
+    for (size_t q = 0; q < flats.size(); ++q) t_star[q] = target[q] - SV::gauge_value(sums, flats[q]);
     const std::vector<double> t = nearest_feasible_shift(t_star, flats, sv.ax, mins.data());
     for (int l = 0; l < n_axes; ++l) {
       double u = 0;
