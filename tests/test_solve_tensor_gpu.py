@@ -177,6 +177,23 @@ def test_coil_shape_all_components(lib):
     print("coil all components:", info["iterations"], "iterations", flush=True)
 
 
+def test_order_of_axes_and_modalities_does_not_matter(lib):
+    """The coordinate layout follows the order of the modalities and of their
+    axes; the solution must not (within the parity bar)."""
+    E = low_rank_tensor_spectra((12, 9, 7), 3, seed=21)
+    rng = np.random.default_rng(22)
+    E = E + [np.sort(rng.uniform(0.5, 30.0, r))[::-1].copy() for r in (5, 8, 6)]
+    mods = [(0, 1, 2), (0, 3), (0, 4, 5)]
+    a, _ = _gpu_solve(lib, E, mods)
+    perm = [4, 2, 0, 5, 1, 3]                              # new axis q is old axis perm[q]
+    inv = {old: new for new, old in enumerate(perm)}
+    mods_p = [tuple(inv[x] for x in reversed(m)) for m in reversed(mods)]
+    b, _ = _gpu_solve(lib, [E[perm[q]] for q in range(6)], mods_p)
+    for q in range(6):
+        x, y = b[q], a[perm[q]]
+        assert np.all(np.abs(x - y) <= 1e-10 * np.abs(y) + 1e-12 * np.max(y)), q
+
+
 def test_warm_start_and_determinism(lib):
     E = low_rank_tensor_spectra((20, 32, 32), 4, seed=2)
     mods = [(0, 1, 2)]
