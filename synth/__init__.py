@@ -39,7 +39,7 @@ __all__ = [
     "cell_factor_proxy",
     "csr_proxy",
     "spectrum_proxy",
-    "config",
+    "workload",
     "ROW_BLOCK",
 ]
 
@@ -47,17 +47,17 @@ ROW_BLOCK = 4096
 FACTOR_RANK = 8
 ALPHA = 2.0
 
-# The workloads: sizes and generator parameters of the five configurations.
-CONFIGS = {
-    0: dict(n=2000, p=500, clusters=8, zipf=False, beta0=0.0, r_c=500, r_g=500, k=10, seed=1000),
-    1: dict(n=100_000, p=2000, clusters=20, zipf=True, beta0=0.0, r_c=50, r_g=2000, k=10, seed=2000),
-    2: dict(n=1_000_000, p=20_000, clusters=40, zipf=True, beta0=None, density=0.05,
-            r_c=100, r_g=20_000, k=10, seed=3000),
+# The workloads by shape: sizes and generator parameters.
+WORKLOADS = {
+    "2000x500": dict(n=2000, p=500, clusters=8, zipf=False, beta0=0.0, r_c=500, r_g=500, k=10, seed=1000),
+    "100kx2000": dict(n=100_000, p=2000, clusters=20, zipf=True, beta0=0.0, r_c=50, r_g=2000, k=10, seed=2000),
+    "1Mx20k": dict(n=1_000_000, p=20_000, clusters=40, zipf=True, beta0=None, density=0.05,
+                   r_c=100, r_g=20_000, k=10, seed=3000),
 }
 
 
-def config(i: int) -> dict:
-    return dict(CONFIGS[i])
+def workload(name: str) -> dict:
+    return dict(WORKLOADS[name])
 
 
 def zipf_sizes(n: int, n_clusters: int, s: float = 1.2) -> np.ndarray:
