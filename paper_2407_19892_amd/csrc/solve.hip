@@ -870,15 +870,18 @@ struct TensorSolver : Core {
       h_axis_ptr[l + 1] = h_axis_ptr[l] + (int)per_axis[l].size();
       for (int k : per_axis[l]) h_axis_jobs.push_back(k);
     }
-    for (auto& m : sets) {   // each modality's log terms once, from its first axis
+    for (auto& m : sets) {   // each modality's log terms once, from its largest-rank axis (most waves)
+      int own = m[0];
+      for (int a : m)
+        if (ax[a].r > ax[own].r) own = a;
       TupleJob j{};
-      j.own = m[0];
-      const std::vector<int> o = others(m, m[0], -1);
+      j.own = own;
+      const std::vector<int> o = others(m, own, -1);
       j.n = (int)o.size();
       for (int u = 0; u < j.n; ++u) j.other[u] = o[u];
       j.first_wave = log_waves;
       j.part = log_waves;
-      log_waves += ax[m[0]].r;
+      log_waves += ax[own].r;
       h_log_jobs.push_back(j);
     }
     log_parts = log_waves;
