@@ -267,6 +267,61 @@ __global__ void __launch_bounds__(256) cross_jobs_kernel(const double* __restric
   S[(size_t)(ax_off[jb.b] + j) * ldS + ax_off[jb.a] + i] = acc;
 }
 
+// Schur complement of the shared block after the private blocks' forward
+// elimination (S seen column-major, leading dimension ld: the shared block
+// C(i, j) at S[(K + j) ld + K + i], the private rows of the shared columns
+// B(k, i) = S[(K + i) ld + k], k < K):  C(i, j) -= sum_{k<K} B(k, i) B(k, j) for
+// i >= j.  One 16 x 16 tile and one of `slices` equal ranges of k per
+// workgroup (blockIdx.z; tiles above the diagonal exit), k staged in LDS 64 at
+// a time; each range's sums go to part[z][i][j] and hub_schur_reduce_kernel
+// subtracts them in range order (fixed summation order throughout).
+__global__ void __launch_bounds__(256) hub_schur_kernel(const double* __restrict__ S, int ld, int K, int nh,
+                                                        int slices, double* __restrict__ part) {
+  const int bi = blockIdx.y, bj = blockIdx.x, z = blockIdx.z;
+  if (bj > bi) return;
+  __shared__ double bI[16][65], bJ[16][65];
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  const int i = bi * 16 + ti, j = bj * 16 + tj;
+  const int per = (K + slices - 1) / slices;
+  const int kb = z * per, ke = min(K, kb + per);
+  double acc = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += 64) {
+    for (int q = threadIdx.x; q < 16 * 64; q += 256) {
+      const int rr = q >> 6, kk = q & 63, k = k0 + kk;
+      const int ir = bi * 16 + rr, jr = bj * 16 + rr;
+      bI[rr][kk] = (k < ke && ir < nh) ? S[(size_t)(K + ir) * ld + k] : 0.0;
+      bJ[rr][kk] = (k < ke && jr < nh) ? S[(size_t)(K + jr) * ld + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 64; ++kk) acc += bI[ti][kk] * bJ[tj][kk];
+    __syncthreads();
+  }
+  if (i < nh && j < nh && i >= j) part[((size_t)z * nh + i) * nh + j] = acc;
+}
+
+__global__ void hub_schur_reduce_kernel(double* __restrict__ S, int ld, int K, int nh, int slices,
+                                        const double* __restrict__ part) {
+  const int i = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > i || i >= nh) return;
+  double a = 0.0;
+  for (int z = 0; z < slices; ++z) a += part[((size_t)z * nh + i) * nh + j];
+  S[(size_t)(K + j) * ld + K + i] -= a;
+}
+
+// rhs[K + i] -= sum_{k<K} B(k, i) rhs[k] (B as in hub_schur_kernel); one wave per i.
+__global__ void __launch_bounds__(256) hub_rhs_kernel(const double* __restrict__ S, int ld, int K, int nh,
+                                                      double* __restrict__ rhs) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nh) return;
+  const double* __restrict__ col = S + (size_t)(K + i) * ld;
+  double a = 0.0;
+  for (int k = lane; k < K; k += 64) a += col[k] * rhs[k];
+  a = wave_sum(a);
+  if (lane == 0) rhs[K + i] -= a;
+}
+
 // Diagonal (1+rho) h, right-hand side -g and activity flags of every coordinate
 // (S's diagonal holds zeros before).
 __global__ void tensor_diag_kernel(const double* __restrict__ h, const double* __restrict__ g,
@@ -822,6 +877,8 @@ struct TensorSolver : Core {
   std::vector<std::pair<size_t, size_t>> groups;   // (offset, size)
   size_t hub_off = 0;
   int* ginfo = nullptr;                           // factorisation flags of the groups
+  double* hub_part = nullptr;                     // partial Schur sums of the shared block
+  int hub_slices = 1;
   std::vector<TupleJob> h_grad_jobs, h_log_jobs;
   std::vector<CrossJob> h_cross_jobs;
   std::vector<CrossTerm> h_terms;
@@ -912,8 +969,18 @@ struct TensorSolver : Core {
     const size_t b_ap = al((L + 1) * sizeof(int)), b_aj = al(h_axis_jobs.size() * sizeof(int));
     const size_t b_p = al((size_t)part * sizeof(double)), b_lg = al((size_t)log_parts * sizeof(double));
     const size_t b_gi = al((groups.size() + 1) * sizeof(int));
+    // k ranges of the shared block's Schur update: enough workgroups to fill the
+    // chip when the block is small, partial sums at most 64 MiB
+    const size_t nh = T - hub_off, tiles = (nblk(nh, 16) * (nblk(nh, 16) + 1)) / 2;
+    hub_slices = 1;
+    if (nh > 0 && hub_off > 0) {
+      const size_t want = std::max<size_t>(1, 2048 / std::max<size_t>(tiles, 1));
+      const size_t by_k = (hub_off + 255) / 256, by_mem = std::max<size_t>(1, ((size_t)64 << 20) / (8 * nh * nh));
+      hub_slices = (int)std::max<size_t>(1, std::min(want, std::min(by_k, by_mem)));
+    }
+    const size_t b_hp = al((size_t)hub_slices * nh * nh * sizeof(double) + 8);
     void* w2;
-    GMGM_TRY(ws_get(c, WS_SOLVE2, b_gj + b_lj + b_cj + b_tm + b_ap + b_aj + 2 * b_p + b_lg + b_gi, &w2));
+    GMGM_TRY(ws_get(c, WS_SOLVE2, b_gj + b_lj + b_cj + b_tm + b_ap + b_aj + 2 * b_p + b_lg + b_gi + b_hp, &w2));
     char* q = (char*)w2;
     grad_jobs = (TupleJob*)q;
     q += b_gj;
@@ -934,6 +1001,8 @@ struct TensorSolver : Core {
     plg = (double*)q;
     q += b_lg;
     ginfo = (int*)q;
+    q += b_gi;
+    hub_part = (double*)q;
     auto up = [&](void* dst, const void* src, size_t bytes) -> gmgm_status {
       if (bytes) GMGM_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
       return GMGM_OK;
@@ -1005,8 +1074,9 @@ struct TensorSolver : Core {
   // that the library routines take (leading dimension nS).  Per group g:
   // A_g = L_g L_g^T, B_g <- L_g^-1 B_g (B_g: the group's rows of the shared
   // columns), y_g = L_g^-1 rhs_g; then the shared block's Schur complement
-  // C - sum_g B_g^T B_g (one rank-k update: the groups are contiguous) and
-  // right-hand side rhs_h - sum_g B_g^T y_g, its Cholesky solve, y <- y - B x_h
+  // C - sum_g B_g^T B_g (hub_schur_kernel: the groups are contiguous) and
+  // right-hand side rhs_h - sum_g B_g^T y_g (hub_rhs_kernel), its Cholesky
+  // solve, y <- y - B x_h
   // and x_g = L_g^-T y_g.  Groups of one common size go through strided-batched
   // calls.  Flags of the factorisations: ginfo[g], ginfo[G] for the shared block.
   gmgm_status block_arrow_solve() {
@@ -1045,8 +1115,12 @@ struct TensorSolver : Core {
     if (nh > 0) {
       double* C = S + hub_off * nS + hub_off;
       if (k > 0) {
-        chk(rocblas_dsyrk(bh, rocblas_fill_lower, rocblas_operation_transpose, nh, k, &minus, Bh, ld, &one, C, ld));
-        chk(rocblas_dgemv(bh, rocblas_operation_transpose, k, nh, &minus, Bh, ld, rhs, 1, &one, rhs + hub_off, 1));
+        const unsigned nt = nblk(nh, 16);
+        hipLaunchKernelGGL(hub_schur_kernel, dim3(nt, nt, (unsigned)hub_slices), dim3(256), 0, st, S, (int)ld, (int)k,
+                           (int)nh, hub_slices, hub_part);
+        hipLaunchKernelGGL(hub_schur_reduce_kernel, dim3(nblk(nh), (unsigned)nh), dim3(256), 0, st, S, (int)ld, (int)k,
+                           (int)nh, hub_slices, hub_part);
+        hipLaunchKernelGGL(hub_rhs_kernel, dim3(nblk(nh, 4)), dim3(256), 0, st, S, (int)ld, (int)k, (int)nh, rhs);
       }
       chk(rocsolver_dpotrf(bh, rocblas_fill_lower, nh, C, ld, ginfo + G));
       chk(rocsolver_dpotrs(bh, rocblas_fill_lower, nh, 1, C, ld, rhs + hub_off, nh));
