@@ -1071,9 +1071,10 @@ struct TensorSolver : Core {
 
   // Solves S x = rhs in place (S symmetric positive definite, block-arrow).
   // S is symmetric, so its row-major storage is also the column-major matrix
-  // that the library routines take (leading dimension nS).  Per group g:
-  // A_g = L_g L_g^T, B_g <- L_g^-1 B_g (B_g: the group's rows of the shared
-  // columns), y_g = L_g^-1 rhs_g; then the shared block's Schur complement
+  // that the library routines take (leading dimension nS); rhs directly follows
+  // S, so it is that matrix's column nS.  Per group g: A_g = L_g L_g^T, then
+  // one triangular solve with the group's rows of the shared columns and of
+  // rhs (B_g <- L_g^-1 B_g, y_g = L_g^-1 rhs_g); then the shared block's Schur complement
   // C - sum_g B_g^T B_g (hub_schur_kernel: the groups are contiguous) and
   // right-hand side rhs_h - sum_g B_g^T y_g (hub_rhs_kernel), its Cholesky
   // solve, y <- y - B x_h
@@ -1095,21 +1096,15 @@ struct TensorSolver : Core {
       const rocblas_int p = (rocblas_int)groups[0].second;
       const rocblas_stride sa = (rocblas_stride)p * (ld + 1);
       chk(rocsolver_dpotrf_strided_batched(bh, rocblas_fill_lower, p, S, ld, sa, ginfo, G));
-      if (nh > 0)
-        chk(rocblas_dtrsm_strided_batched(bh, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                                          rocblas_diagonal_non_unit, p, nh, &one, S, ld, sa, Bh, ld, p, G));
-      chk(rocblas_dtrsv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, p,
-                                        S, ld, sa, rhs, 1, p, G));
+      chk(rocblas_dtrsm_strided_batched(bh, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                                        rocblas_diagonal_non_unit, p, nh + 1, &one, S, ld, sa, Bh, ld, p, G));
     } else {
       for (rocblas_int q = 0; q < G; ++q) {
         const rocblas_int o = (rocblas_int)groups[q].first, p = (rocblas_int)groups[q].second;
         double* A = S + (size_t)o * nS + o;
         chk(rocsolver_dpotrf(bh, rocblas_fill_lower, p, A, ld, ginfo + q));
-        if (nh > 0)
-          chk(rocblas_dtrsm(bh, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                            rocblas_diagonal_non_unit, p, nh, &one, A, ld, Bh + o, ld));
-        chk(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, p, A, ld,
-                          rhs + o, 1));
+        chk(rocblas_dtrsm(bh, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                          rocblas_diagonal_non_unit, p, nh + 1, &one, A, ld, Bh + o, ld));
       }
     }
     if (nh > 0) {
