@@ -769,8 +769,9 @@ struct Solver : Core {
     return GMGM_OK;
   }
 
-  // sum E x into scal[0] and the log sum into scal[1]
-  gmgm_status nll_launch(const double* x) {
+  // sum E x into out[0] and the log sum into out[1] (out: scal when null)
+  gmgm_status nll_launch(const double* x, double* out = nullptr) {
+    if (!out) out = scal;
     for (int l = 0; l < L; ++l) {
       int first = 1;
       for (auto& m : mods)
@@ -782,9 +783,9 @@ struct Solver : Core {
         }
       if (first) GMGM_HIP(c, hipMemsetAsync(lg + ax[l].off, 0, ax[l].r * sizeof(double), st));
     }
-    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, scal);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, out);
     hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, lg, (const double*)nullptr,
-                       (int)T, scal + 1);
+                       (int)T, out + 1);
     return GMGM_OK;
   }
 
@@ -1025,13 +1026,14 @@ struct TensorSolver : Core {
     return GMGM_OK;
   }
 
-  // sum E x into scal[0] and the log sum into scal[1]
-  gmgm_status nll_launch(const double* x) {
+  // sum E x into out[0] and the log sum into out[1] (out: scal when null)
+  gmgm_status nll_launch(const double* x, double* out = nullptr) {
+    if (!out) out = scal;
     hipLaunchKernelGGL(tuple_jobs_kernel, dim3(nblk(log_waves, 4)), dim3(256), 0, st, x, ax_off, ax_r, log_jobs,
                        (int)h_log_jobs.size(), log_waves, 1, (double*)nullptr, (double*)nullptr, plg);
-    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, scal);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, out);
     hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, plg, (const double*)nullptr, log_parts,
-                       scal + 1);
+                       out + 1);
     return GMGM_OK;
   }
 
@@ -1221,21 +1223,32 @@ gmgm_status drive(SV& sv, const double* const* E, const double* eps, const doubl
       GMGM_TRY(sv.nll(sv.lam, &f0));
       // steps may drift along flat directions (the NLL is constant there)
       GMGM_TRY(sv.direction(std::min(1e-2, kres)));
+      // Backtracking over alpha = 2^-s, s = 0 .. 59: the first length that
+      // satisfies Armijo is taken.  alpha = 1 is tried alone, later lengths
+      // eight at a time with one read-back; the choice and the trial point are
+      // those of trying the lengths one by one.
       double alpha = 1.0;
       bool accepted = false;
-      for (int ls = 0; ls < 60; ++ls) {
-        sv.trial_point(alpha);
-        hipLaunchKernelGGL(pred_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.g, sv.d, sv.lam, sv.trial,
-                           sv.act, (int)T, alpha, sv.scal + 2);
-        GMGM_TRY(sv.nll_launch(sv.trial));
-        double v[3];
-        GMGM_TRY(sv.fetch(v, sv.scal, 3));
-        const double f1 = 0.5 * (v[0] - v[1]), pred = v[2];
-        if (f1 <= f0 + 1e-4 * pred || std::fabs(pred) <= 1e-13 * (std::fabs(f0) + 1.0)) {
-          accepted = true;
-          break;
+      for (int tried = 0; !accepted && tried < 60;) {
+        const int nb = tried == 0 ? 1 : std::min(8, 60 - tried);
+        for (int b = 0; b < nb; ++b) {
+          const double a = std::ldexp(1.0, -(tried + b));
+          sv.trial_point(a);
+          hipLaunchKernelGGL(pred_kernel, dim3(1), dim3(RED_THREADS), 0, st, sv.g, sv.d, sv.lam, sv.trial,
+                             sv.act, (int)T, a, sv.scal + 3 * b + 2);
+          GMGM_TRY(sv.nll_launch(sv.trial, sv.scal + 3 * b));
         }
-        alpha *= 0.5;
+        double v[24];
+        GMGM_TRY(sv.fetch(v, sv.scal, 3 * nb));
+        for (int b = 0; b < nb && !accepted; ++b) {
+          const double f1 = 0.5 * (v[3 * b] - v[3 * b + 1]), pred = v[3 * b + 2];
+          if (f1 <= f0 + 1e-4 * pred || std::fabs(pred) <= 1e-13 * (std::fabs(f0) + 1.0)) {
+            accepted = true;
+            alpha = std::ldexp(1.0, -(tried + b));
+            if (b != nb - 1) sv.trial_point(alpha);   // trial holds the last length tried
+          }
+        }
+        tried += nb;
       }
       if (!accepted) {
         stalled = true;
