@@ -334,6 +334,46 @@ __global__ void tensor_diag_kernel(const double* __restrict__ h, const double* _
   act_hub[c] = act[c];
 }
 
+// pair_sums_kernel's s1, s2 for a short x against a long y: nsplit waves per i,
+// each over one of nsplit equal ranges of j, partial sums to p1, p2 [s][i];
+// pair_merge_kernel adds them in range order.
+__global__ void __launch_bounds__(256) pair_sums_split_kernel(const double* __restrict__ x, int nx,
+                                                              const double* __restrict__ y, int ny, int nsplit,
+                                                              double* __restrict__ p1, double* __restrict__ p2) {
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nx * nsplit) return;
+  const int i = w / nsplit, sp = w % nsplit;
+  const int per = (ny + nsplit - 1) / nsplit;
+  const int jb = sp * per, je = min(ny, jb + per);
+  const double xi = x[i];
+  double a1 = 0, c1 = 0, a2 = 0, c2 = 0;
+  for (int j = jb + lane; j < je; j += 64) {
+    const double r = 1.0 / (xi + y[j]);
+    neumaier(a1, c1, r);
+    neumaier(a2, c2, r * r);
+  }
+  a1 = wave_sum(a1) + wave_sum(c1);
+  a2 = wave_sum(a2) + wave_sum(c2);
+  if (lane == 0) {
+    p1[(size_t)sp * nx + i] = a1;
+    p2[(size_t)sp * nx + i] = a2;
+  }
+}
+
+__global__ void pair_merge_kernel(int nx, int nsplit, const double* __restrict__ p1, const double* __restrict__ p2,
+                                  double* __restrict__ s1, double* __restrict__ s2, int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nx) return;
+  double a1 = 0.0, a2 = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    a1 += p1[(size_t)sp * nx + i];
+    a2 += p2[(size_t)sp * nx + i];
+  }
+  s1[i] = accumulate ? s1[i] + a1 : a1;
+  s2[i] = accumulate ? s2[i] + a2 : a2;
+}
+
 // g = (E - s1)/2, h = s2/2, the active set and each coordinate's KKT term:
 // |g| / (E/2) when free, max(0, -g) / (E/2) at the bound.
 __global__ void assemble_kernel(const double* __restrict__ E, const double* __restrict__ lam,
@@ -358,21 +398,27 @@ __global__ void assemble_kernel(const double* __restrict__ E, const double* __re
 //   B[i][j] = 1/2 (x_i + y_j)^-2,
 // and, when with_rhs, rhs[K1_i] += sum_{free j} B1[i][j] g_m[j] / ((1+rho) h_m[j]).
 // A 16 x 16 tile of S per workgroup.
+// The leaf's j range is split into gridDim.z equal parts: part z writes its
+// sums to part[z][i][k] (and rpart[z][i]); schur_leaf_merge_kernel applies
+// them to S and rhs in part order.
 __global__ void __launch_bounds__(256) schur_leaf_kernel(
-    const double* __restrict__ x1, int n1, int off1, const double* __restrict__ x2, int n2, int off2,
+    const double* __restrict__ x1, int n1, const double* __restrict__ x2, int n2,
     const double* __restrict__ ym, int nm, const int* __restrict__ act_m,
     const double* __restrict__ hm, const double* __restrict__ gm, double damp,
-    double* __restrict__ S, int ldS, double* __restrict__ rhs, int with_rhs) {
+    double* __restrict__ part, double* __restrict__ rpart, int with_rhs) {
   __shared__ double b1[16][65], b2[16][65], w[64], wg[64];
   const int ti = threadIdx.x >> 4, tk = threadIdx.x & 15;
   const int i = blockIdx.y * 16 + ti, k = blockIdx.x * 16 + tk;
+  const int z = blockIdx.z, nz = gridDim.z;
+  const int per = ((nm + nz - 1) / nz + 63) / 64 * 64;
+  const int jb = z * per, je = min(nm, jb + per);
   double acc = 0.0, racc = 0.0;
-  for (int j0 = 0; j0 < nm; j0 += 64) {
+  for (int j0 = jb; j0 < je; j0 += 64) {
     for (int q = threadIdx.x; q < 16 * 64; q += 256) {
       const int rr = q >> 6, jj = q & 63, j = j0 + jj;
       const int ir = blockIdx.y * 16 + rr, kr = blockIdx.x * 16 + rr;
       double v1 = 0.0, v2 = 0.0;
-      if (j < nm && !act_m[j]) {
+      if (j < je && !act_m[j]) {
         if (ir < n1) {
           const double s = x1[ir] + ym[j];
           v1 = 0.5 / (s * s);
@@ -387,7 +433,7 @@ __global__ void __launch_bounds__(256) schur_leaf_kernel(
     }
     if (threadIdx.x < 64) {
       const int j = j0 + threadIdx.x;
-      const bool fr = j < nm && !act_m[j];
+      const bool fr = j < je && !act_m[j];
       w[threadIdx.x] = fr ? 1.0 / (damp * hm[j]) : 0.0;
       wg[threadIdx.x] = fr ? gm[j] / (damp * hm[j]) : 0.0;
     }
@@ -398,8 +444,23 @@ __global__ void __launch_bounds__(256) schur_leaf_kernel(
       for (int jj = 0; jj < 64; ++jj) racc += b1[ti][jj] * wg[jj];
     __syncthreads();
   }
-  if (i < n1 && k < n2) S[(size_t)(off1 + i) * ldS + off2 + k] -= acc;
-  if (with_rhs && blockIdx.x == 0 && tk == 0 && i < n1) rhs[off1 + i] += racc;
+  if (i < n1 && k < n2) part[((size_t)z * n1 + i) * n2 + k] = acc;
+  if (with_rhs && blockIdx.x == 0 && tk == 0 && i < n1) rpart[(size_t)z * n1 + i] = racc;
+}
+
+__global__ void schur_leaf_merge_kernel(int n1, int off1, int n2, int off2, int nz,
+                                        const double* __restrict__ part, const double* __restrict__ rpart,
+                                        double* __restrict__ S, int ldS, double* __restrict__ rhs, int with_rhs) {
+  const int i = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n1 || k >= n2) return;
+  double a = 0.0;
+  for (int z = 0; z < nz; ++z) a += part[((size_t)z * n1 + i) * n2 + k];
+  S[(size_t)(off1 + i) * ldS + off2 + k] -= a;
+  if (with_rhs && k == 0) {
+    double r = 0.0;
+    for (int z = 0; z < nz; ++z) r += rpart[(size_t)z * n1 + i];
+    rhs[off1 + i] += r;
+  }
 }
 
 // Cross block between hub axes K1 (rows) and K2 (columns): S[K1][K2] += B, S[K2][K1] += B^T.
@@ -759,6 +820,50 @@ struct Solver : Core {
   std::vector<std::pair<int, int>> mods;
   std::vector<int> hub, is_hub;
   std::vector<size_t> hoff;
+  double* split_buf = nullptr;   // partial sums of the split pair-sum and Schur-leaf passes
+
+  // Ranges of the long axis for one short axis' pair sums (enough waves to fill
+  // the chip, at least 256 partners each); 1 = no split.
+  static int pair_splits(int nx, int ny) {
+    if (nx >= 2048) return 1;
+    return std::max(1, std::min({64, (4096 + nx - 1) / nx, (ny + 255) / 256}));
+  }
+  // Ranges of a leaf axis for one Schur block (about 1024 workgroups, at least
+  // 256 leaf coordinates each, partial sums at most 64 MiB).
+  static int leaf_splits(int n1, int n2, int nm) {
+    const long tiles = (long)nblk(n1, 16) * nblk(n2, 16);
+    const long by_mem = std::max<long>(1, (64L << 20) / (8L * n1 * n2 + 8L * n1));
+    return (int)std::max<long>(
+        1, std::min<long>({64L, std::max<long>(1, 1024 / tiles), (long)(nm + 255) / 256, by_mem}));
+  }
+
+  // workspace for the largest split pass (WS_SOLVE2)
+  gmgm_status plan_splits() {
+    size_t need = 16;
+    for (int l = 0; l < L; ++l)
+      for (auto& m : mods) {
+        const int other = m.first == l ? m.second : m.second == l ? m.first : -1;
+        if (other < 0) continue;
+        need = std::max(need, 2 * (size_t)pair_splits(ax[l].r, ax[other].r) * ax[l].r);
+      }
+    for (int m = 0; m < L; ++m) {
+      if (is_hub[m]) continue;
+      for (auto& md : mods) {
+        const int K1 = md.first == m ? md.second : md.second == m ? md.first : -1;
+        if (K1 < 0) continue;
+        for (auto& md2 : mods) {
+          const int K2 = md2.first == m ? md2.second : md2.second == m ? md2.first : -1;
+          if (K2 < 0) continue;
+          const size_t nz = leaf_splits(ax[K1].r, ax[K2].r, ax[m].r);
+          need = std::max(need, nz * ax[K1].r * ax[K2].r + nz * ax[K1].r);
+        }
+      }
+    }
+    void* w;
+    GMGM_TRY(ws_get(c, WS_SOLVE2, need * sizeof(double), &w));
+    split_buf = (double*)w;
+    return GMGM_OK;
+  }
 
   // NLL(x) = 1/2 (sum E x - sum log); each modality's log terms counted once.
   gmgm_status nll(const double* x, double* out) {
@@ -772,17 +877,17 @@ struct Solver : Core {
   // sum E x into out[0] and the log sum into out[1] (out: scal when null)
   gmgm_status nll_launch(const double* x, double* out = nullptr) {
     if (!out) out = scal;
-    for (int l = 0; l < L; ++l) {
-      int first = 1;
-      for (auto& m : mods)
-        if (m.first == l) {
-          hipLaunchKernelGGL(pair_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off,
-                             ax[l].r, x + ax[m.second].off, ax[m.second].r, (double*)nullptr,
-                             (double*)nullptr, lg + ax[l].off, first ? 0 : 1);
-          first = 0;
-        }
-      if (first) GMGM_HIP(c, hipMemsetAsync(lg + ax[l].off, 0, ax[l].r * sizeof(double), st));
+    // each modality's log terms from its larger axis (one wave per entry)
+    std::vector<int> written(L, 0);
+    for (auto& m : mods) {
+      const int l = ax[m.second].r > ax[m.first].r ? m.second : m.first;
+      const int o = l == m.first ? m.second : m.first;
+      hipLaunchKernelGGL(pair_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off, ax[l].r,
+                         x + ax[o].off, ax[o].r, (double*)nullptr, (double*)nullptr, lg + ax[l].off, written[l]);
+      written[l] = 1;
     }
+    for (int l = 0; l < L; ++l)
+      if (!written[l]) GMGM_HIP(c, hipMemsetAsync(lg + ax[l].off, 0, ax[l].r * sizeof(double), st));
     hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, Ec, x, (int)T, out);
     hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(RED_THREADS), 0, st, lg, (const double*)nullptr,
                        (int)T, out + 1);
@@ -796,9 +901,19 @@ struct Solver : Core {
       for (auto& m : mods) {
         const int other = m.first == l ? m.second : m.second == l ? m.first : -1;
         if (other < 0) continue;
-        hipLaunchKernelGGL(pair_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off,
-                           ax[l].r, x + ax[other].off, ax[other].r, s1 + ax[l].off, s2 + ax[l].off,
-                           (double*)nullptr, first ? 0 : 1);
+        const int ns = pair_splits(ax[l].r, ax[other].r);
+        if (ns > 1) {
+          double* p1 = split_buf;
+          double* p2 = split_buf + (size_t)ns * ax[l].r;
+          hipLaunchKernelGGL(pair_sums_split_kernel, dim3(nblk((int64_t)ax[l].r * ns, 4)), dim3(256), 0, st,
+                             x + ax[l].off, ax[l].r, x + ax[other].off, ax[other].r, ns, p1, p2);
+          hipLaunchKernelGGL(pair_merge_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, ax[l].r, ns, p1, p2,
+                             s1 + ax[l].off, s2 + ax[l].off, first ? 0 : 1);
+        } else {
+          hipLaunchKernelGGL(pair_sums_kernel, dim3(nblk(ax[l].r, 4)), dim3(256), 0, st, x + ax[l].off,
+                             ax[l].r, x + ax[other].off, ax[other].r, s1 + ax[l].off, s2 + ax[l].off,
+                             (double*)nullptr, first ? 0 : 1);
+        }
         first = 0;
       }
       hipLaunchKernelGGL(assemble_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, Ec + ax[l].off,
@@ -832,11 +947,18 @@ struct Solver : Core {
         if (md.second == m) partners.push_back(md.first);
       }
       for (int K1 : partners)
-        for (int K2 : partners)
-          hipLaunchKernelGGL(schur_leaf_kernel, dim3(nblk(ax[K2].r, 16), nblk(ax[K1].r, 16)), dim3(256),
-                             0, st, lam + ax[K1].off, ax[K1].r, (int)hoff[K1], lam + ax[K2].off,
-                             ax[K2].r, (int)hoff[K2], lam + ax[m].off, ax[m].r, act + ax[m].off,
-                             h + ax[m].off, g + ax[m].off, damp, S, (int)nS, rhs, K1 == K2 ? 1 : 0);
+        for (int K2 : partners) {
+          const int nz = leaf_splits(ax[K1].r, ax[K2].r, ax[m].r);
+          double* part = split_buf;
+          double* rpart = split_buf + (size_t)nz * ax[K1].r * ax[K2].r;
+          const int wr = K1 == K2 ? 1 : 0;
+          hipLaunchKernelGGL(schur_leaf_kernel, dim3(nblk(ax[K2].r, 16), nblk(ax[K1].r, 16), (unsigned)nz),
+                             dim3(256), 0, st, lam + ax[K1].off, ax[K1].r, lam + ax[K2].off, ax[K2].r,
+                             lam + ax[m].off, ax[m].r, act + ax[m].off, h + ax[m].off, g + ax[m].off, damp, part,
+                             rpart, wr);
+          hipLaunchKernelGGL(schur_leaf_merge_kernel, dim3(nblk(ax[K2].r), (unsigned)ax[K1].r), dim3(256), 0, st,
+                             ax[K1].r, (int)hoff[K1], ax[K2].r, (int)hoff[K2], nz, part, rpart, S, (int)nS, rhs, wr);
+        }
     }
     hipLaunchKernelGGL(schur_pin_kernel, dim3(nblk(nS), (unsigned)nS), dim3(256), 0, st, act_hub,
                        (int)nS, S, rhs);
@@ -1351,6 +1473,7 @@ extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64
     return set_err(c, GMGM_E_SHAPE, "the Schur system has %zu unknowns (at most %d)", sv.nS, MAX_HUB);
   GMGM_HIP(c, hipSetDevice(c->device));
   GMGM_TRY(sv.bind_workspace());
+  GMGM_TRY(sv.plan_splits());
   return drive(sv, E, eps, warm, tol, max_iter, lambda_out, info);
 }
 
