@@ -128,6 +128,24 @@ gmgm_status gmgm_recompose_topk(gmgm_ctx_t ctx, int64_t n, int64_t r, const floa
                                 gmgm_topk_stats* stats);
 
 /*
+ * The rounding constant c of the certificate that makes every operand
+ * precision of gmgm_recompose_topk / gmgm_recompose_threshold exact
+ * (Algorithm 1, final loop, read as an exact per-row selection): with W = V
+ * diag(psi), the sweep's approximate value of Psi_ij = W_i . V_j satisfies
+ *   |Psi~_ij - Psi_ij| <= beta_i = c ||W_i||_2 max_j ||V_j||_2,
+ * from the operand format's unit roundoff (FP32 2^-24, BF16 2^-8, FP8 e4m3
+ * 2^-4 plus its subnormal floor; W is rounded to FP32 first), one FP32 ulp per
+ * accumulation step over the padded depth, and Cauchy-Schwarz.
+ *   prec        gmgm_prec value.
+ *   r           the rank, 1 <= r <= 128.
+ *   c_out       host double: c.
+ *   kpad_out    host int32 or NULL: the padded MFMA depth for r.
+ * Host arithmetic only (no context, no device).  GMGM_E_ARG / GMGM_E_SHAPE
+ * for a bad precision or rank.
+ */
+gmgm_status gmgm_rounding_bound(int32_t prec, int64_t r, double* c_out, int32_t* kpad_out);
+
+/*
  * Fused eigen-recomposition with a fixed threshold into CSR: the significance
  * rule of Theorem 3 (keep the statistically significant edges), or any fixed
  * threshold.  For each row i in [row_begin, row_end) of Psi = V diag(psi) V^T,
@@ -467,6 +485,38 @@ gmgm_status gmgm_ws_train_step(gmgm_ctx_t ctx, float* params, float* adam_m, flo
  * lambda_i = exp(curve(u_i)) / E_i.  Asynchronous. */
 gmgm_status gmgm_ws_apply(gmgm_ctx_t ctx, const float* curves, const double* Ec, int64_t rc,
                           const double* Eg, int64_t rg, double* lam_c, double* lam_g);
+
+/*
+ * The learned warm start as two calls (the network, features and loss of the
+ * gmgm_ws_* calls above; it replaces Algorithm 1's start lambda^0 = 1/E).
+ *
+ * weights     the network's parameter vector (gmgm_ws_param_count() FP32,
+ *             device), e.g. from gmgm_ws_init; updated in place by training.
+ * opt_state   device memory of gmgm_warmstart_state_bytes() bytes holding the
+ *             AdamW state: an int64 update count at byte 0, the FP32 decoupled
+ *             weight decay at byte 8, then the first and second moments
+ *             (param_count FP32 each) from byte 256.  gmgm_warmstart_state_init
+ *             zeroes it and sets the weight decay.
+ */
+int64_t gmgm_warmstart_state_bytes(void);
+
+/* Zero the optimiser state and set its weight decay (>= 0).  Asynchronous. */
+gmgm_status gmgm_warmstart_state_init(gmgm_ctx_t ctx, void* opt_state, float weight_decay);
+
+/* out (batch x 1024 FP32, device) = network(feats (batch x 1028 FP32,
+ * device)); 1 <= batch <= 8192.  Asynchronous. */
+gmgm_status gmgm_warmstart_infer(gmgm_ctx_t ctx, const void* weights, int32_t batch, const float* feats,
+                                 float* out);
+
+/* One AdamW step (AdamW: 0.9, 0.999, eps 1e-8; the update count in opt_state
+ * is incremented on the device and gives the bias corrections) on the masked
+ * mean squared error of a batch: feats (batch x 1028), target and mask
+ * (batch x 1024 FP32, device; mask NULL = all ones), learning rate lr >= 0.
+ * loss_out: host float or NULL; when given, the loss before the update is
+ * written and the call synchronises, else it is asynchronous. */
+gmgm_status gmgm_warmstart_train_step(gmgm_ctx_t ctx, void* weights, void* opt_state, int32_t batch,
+                                      const float* feats, const float* target, const float* mask, float lr,
+                                      float* loss_out);
 
 #ifdef __cplusplus
 }

@@ -67,6 +67,7 @@ SIGNATURES = {
     "gmgm_significance_threshold": (ctypes.c_int, [_P, _I64, _I32, ctypes.POINTER(ctypes.c_double),
                                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                                    ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "gmgm_rounding_bound": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
     "gmgm_gram": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
     "gmgm_gram_shifted": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "gmgm_sketch_shifted": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _I64, _P, _I64, _P, _P]),
@@ -81,6 +82,11 @@ SIGNATURES = {
     "gmgm_ws_train_step": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, _P, _P, _P, ctypes.c_float,
                                           ctypes.c_float, ctypes.POINTER(ctypes.c_double), _P]),
     "gmgm_ws_apply": (ctypes.c_int, [_P, _P, _P, _I64, _P, _I64, _P, _P]),
+    "gmgm_warmstart_state_bytes": (_I64, []),
+    "gmgm_warmstart_state_init": (ctypes.c_int, [_P, _P, ctypes.c_float]),
+    "gmgm_warmstart_infer": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
+    "gmgm_warmstart_train_step": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _P, ctypes.c_float,
+                                                 ctypes.POINTER(ctypes.c_float)]),
     "gmgm_csr_transpose": (ctypes.c_int, [_P, Csr, _P, _P, _P]),
     "gmgm_subspace_eig": (ctypes.c_int, [_P, _I32, ctypes.POINTER(Csr), ctypes.POINTER(Csr), _P, _I64, _I32, _I64,
                                          _P, _P]),
@@ -267,6 +273,17 @@ def significance_threshold(d_l: int, d_all, trace_s, alpha: float = 0.05, n_test
     if st != 0:
         raise GmgmError(st, "gmgm_significance_threshold rejected its arguments")
     return out.value
+
+
+def rounding_bound(prec: str, r: int):
+    """(c, kpad): the certificate's rounding constant and padded MFMA depth
+    (see gmgm_rounding_bound; host arithmetic, no device needed)."""
+    c = ctypes.c_double(0.0)
+    kp = _I32(0)
+    st = load().gmgm_rounding_bound(PREC[prec], int(r), ctypes.byref(c), ctypes.byref(kp))
+    if st != 0:
+        raise GmgmError(st, "gmgm_rounding_bound rejected its arguments")
+    return c.value, kp.value
 
 
 @dataclass
@@ -547,6 +564,50 @@ def ws_apply(curves, Ec, Eg):
     _check(c, load().gmgm_ws_apply(c, _ptr(curves), _ptr(Ec), Ec.numel(), _ptr(Eg), Eg.numel(), _ptr(lc), _ptr(lg)))
     return lc, lg
 
+
+
+def warmstart_state(weight_decay: float = 0.0, device=None):
+    """A zeroed AdamW state for warmstart_train_step (see gmgm_warmstart_state_init)."""
+    import torch
+    nbytes = int(load().gmgm_warmstart_state_bytes())
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else int(device))
+    st = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    c = context(dev.index)
+    _check(c, load().gmgm_warmstart_state_init(c, _ptr(st), float(weight_decay)))
+    return st
+
+
+def warmstart_infer(weights, feats, out=None):
+    """out (batch x 1024) = the warm-start network of feats (see gmgm_warmstart_infer)."""
+    import torch
+    _f32_dev(weights, "weights", ws_param_count())
+    _f32_dev(feats, "feats")
+    B = feats.numel() // WS_IN
+    if feats.numel() != B * WS_IN:
+        raise ValueError("feats must be batch x 1028")
+    y = torch.empty(B, WS_OUT, dtype=torch.float32, device=feats.device) if out is None else out
+    c = context(feats.device.index)
+    _check(c, load().gmgm_warmstart_infer(c, _ptr(weights), B, _ptr(feats), _ptr(y)))
+    return y
+
+
+def warmstart_train_step(weights, opt_state, feats, target, mask=None, lr: float = 1e-3, want_loss: bool = True):
+    """One AdamW step with the update count kept in opt_state (see
+    gmgm_warmstart_train_step); returns the loss before the update."""
+    _f32_dev(weights, "weights", ws_param_count())
+    _f32_dev(feats, "feats")
+    B = feats.numel() // WS_IN
+    _f32_dev(target, "target", B * WS_OUT)
+    if mask is not None:
+        _f32_dev(mask, "mask", B * WS_OUT)
+    if opt_state.numel() != int(load().gmgm_warmstart_state_bytes()) or not opt_state.is_cuda:
+        raise ValueError("opt_state must come from warmstart_state()")
+    loss = ctypes.c_float()
+    c = context(feats.device.index)
+    _check(c, load().gmgm_warmstart_train_step(c, _ptr(weights), _ptr(opt_state), B, _ptr(feats), _ptr(target),
+                                               _ptr(mask) if mask is not None else None, float(lr),
+                                               ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
 
 
 # ---------------------------------------------------------------- shared large axis

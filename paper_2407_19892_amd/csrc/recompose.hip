@@ -523,21 +523,32 @@ SweepFn pick_sweep(int prec, int kpad, int C) {
 
 
 // Rounding bound c with |Psi~_ij - Psi_ij| <= c ||W_i||_2 max_j ||V_j||_2 (see header).
+// Operands: a format keeping p significant bits rounds to nearest with relative
+// error at most 2^-p (FP32 p = 24, BF16 p = 8, FP8 e4m3 p = 4, plus e4m3's
+// subnormal floor); W = V diag(psi) is first rounded to FP32, then to the
+// operand format.  Products of BF16 or FP8 operands are exact in FP32.  The
+// MFMA's internal summation order and rounding are not documented, so each of
+// the K additions is charged a full unit in the last place of FP32 (2^-23),
+// which also covers truncating adders.  Cauchy-Schwarz turns the elementwise
+// bound sum_k |W_ik||V_jk| into ||W_i|| ||V_j||.
 double cprec_for(int prec, int kpad) {
-  const double u32 = std::ldexp(1.0, -24);
+  const double u32 = std::ldexp(1.0, -24);     // FP32 rounding of W = V psi
+  const double uacc = std::ldexp(1.0, -23);    // one FP32 ulp per accumulation step
   const double K = kpad + 1;
-  const double gam = K * u32 / (1.0 - K * u32);
+  const double gam = K * uacc / (1.0 - K * uacc);
   double c;
   if (prec == P_F32) {
     c = (1 + u32) * (1 + gam) - 1 + gam;          // W rounding; products and sums rounded
   } else if (prec == P_BF16) {
-    const double d = std::ldexp(1.0, -9);
+    const double d = std::ldexp(1.0, -8);         // BF16: 8 significant bits
     const double dw = (1 + u32) * (1 + d) - 1;
-    c = (1 + dw) * (1 + d) * (1 + gam) - 1;        // bf16 products are exact in FP32
+    c = (1 + dw) * (1 + d) * (1 + gam) - 1;
   } else {
-    const double d = std::ldexp(1.0, -4);
+    const double d = std::ldexp(1.0, -4);         // e4m3: 4 significant bits
     const double dw = (1 + u32) * (1 + d) - 1;
-    const double fl = std::ldexp(1.0, -10) / 224.0; // subnormal floor per unit of row/tile max
+    // subnormal floor: half of e4m3's smallest spacing 2^-9 in scaled units,
+    // per unit of the row / tile maximum, which is scaled above 224
+    const double fl = std::ldexp(1.0, -10) / 224.0;
     c = (1 + dw) * (1 + d) * (1 + gam) - 1 + 2 * (1 + d) * std::sqrt((double)kpad) * fl * (1 + gam) +
         kpad * fl * fl;
   }
@@ -1312,4 +1323,13 @@ extern "C" gmgm_status gmgm_significance_threshold(gmgm_ctx_t c, int64_t d_l, in
   *thr_out = 2.0 * upper_normal_quantile(p) * std::sqrt((double)d_l / denom);
   return GMGM_OK;
 #undef SIG_ERR
+}
+
+extern "C" gmgm_status gmgm_rounding_bound(int32_t prec, int64_t r, double* c_out, int32_t* kpad_out) {
+  if (prec < 0 || prec > 2 || !c_out) return GMGM_E_ARG;
+  if (r < 1 || r > 128) return GMGM_E_SHAPE;
+  const int kpad = kpad_for(prec, (int)r);
+  *c_out = cprec_for(prec, kpad);
+  if (kpad_out) *kpad_out = kpad;
+  return GMGM_OK;
 }

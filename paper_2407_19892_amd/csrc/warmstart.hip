@@ -197,10 +197,19 @@ __global__ void colsum_kernel(const float* __restrict__ dZ, int rows, int N, flo
   g[n] = s;
 }
 
+// One AdamW update.  The bias corrections 1 - 0.9^t and 1 - 0.999^t and the
+// weight decay come from the host (bc1, bc2, wd), or, when bcp is given, from
+// bcp[0..2] (written on the device by adam_count_kernel).
 __global__ void adamw_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                             const float* __restrict__ g, int64_t n, float lr, float wd, float bc1, float bc2) {
+                             const float* __restrict__ g, int64_t n, float lr, float wd, float bc1, float bc2,
+                             const float* __restrict__ bcp) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (bcp) {
+    bc1 = bcp[0];
+    bc2 = bcp[1];
+    wd = bcp[2];
+  }
   const float gi = g[i];
   const float mi = 0.9f * m[i] + 0.1f * gi;
   const float vi = 0.999f * v[i] + 0.001f * gi * gi;
@@ -208,6 +217,34 @@ __global__ void adamw_kernel(float* __restrict__ p, float* __restrict__ m, float
   v[i] = vi;
   const float mh = mi / bc1, vh = vi / bc2;
   p[i] -= lr * (mh / (sqrtf(vh) + 1e-8f) + wd * p[i]);
+}
+
+// Optimiser state of gmgm_warmstart_train_step: a header (update count, weight
+// decay) and the two moment vectors.
+struct OptHeader {
+  int64_t step;
+  float weight_decay;
+};
+constexpr int64_t OPT_M = 256;                                   // byte offset of m
+constexpr int64_t OPT_V = OPT_M + N_PARAMS * (int64_t)sizeof(float);
+constexpr int64_t OPT_BYTES = OPT_V + N_PARAMS * (int64_t)sizeof(float);
+
+// t = ++step; bc = {1 - 0.9^t, 1 - 0.999^t, weight decay} (FP64 powers, rounded once).
+__global__ void adam_count_kernel(OptHeader* __restrict__ h, float* __restrict__ bc) {
+  const int64_t t = ++h->step;
+  bc[0] = (float)(1.0 - pow(0.9, (double)t));
+  bc[1] = (float)(1.0 - pow(0.999, (double)t));
+  bc[2] = h->weight_decay;
+}
+
+__global__ void opt_init_kernel(char* __restrict__ state, float wd) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i == 0) {
+    OptHeader* h = (OptHeader*)state;
+    h->step = 0;
+    h->weight_decay = wd;
+  }
+  if (i < 2 * N_PARAMS) ((float*)(state + OPT_M))[i] = 0.0f;
 }
 
 // Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) for every weight and bias of a layer,
@@ -316,15 +353,14 @@ extern "C" gmgm_status gmgm_ws_forward(gmgm_ctx_t c, const float* params, int32_
   return GMGM_OK;
 }
 
-extern "C" gmgm_status gmgm_ws_train_step(gmgm_ctx_t c, float* params, float* adam_m, float* adam_v, int64_t step,
-                                          int32_t batch, const float* feats, const float* target, const float* mask,
-                                          float lr, float weight_decay, double* loss_out, float* grad_out) {
-  GMGM_CHECK_CTX(c);
-  if (!params || !adam_m || !adam_v || !feats || !target) return set_err(c, GMGM_E_ARG, "null pointer argument");
-  if (batch < 1 || batch > MAX_BATCH) return set_err(c, GMGM_E_SHAPE, "batch must be in [1, %d]", MAX_BATCH);
-  if (step < 1 || !(lr >= 0) || !(weight_decay >= 0))
-    return set_err(c, GMGM_E_ARG, "need step >= 1, lr >= 0, weight_decay >= 0");
-  GMGM_HIP(c, hipSetDevice(c->device));
+namespace gmgm_ws {
+// One training step: forward, masked MSE, backward, AdamW.  The update count
+// and weight decay come from the host (step >= 1, weight_decay) or, with
+// `state`, from the device header (incremented there).
+static gmgm_status train_impl(gmgm_ctx* c, float* params, float* adam_m, float* adam_v, int64_t step,
+                              float weight_decay, OptHeader* state, int32_t batch, const float* feats,
+                              const float* target, const float* mask, float lr, double* loss_out,
+                              float* grad_out) {
   hipStream_t st = c->stream;
   const int B = batch;
   Acts a;
@@ -335,6 +371,7 @@ extern "C" gmgm_status gmgm_ws_train_step(gmgm_ctx_t c, float* params, float* ad
   void* ws;
   GMGM_TRY(ws_get(c, WS_MLP1, 64, &ws));
   double* scal = (double*)ws;
+  float* bcp = (float*)((char*)ws + 32);
 
   forward(st, params, B, feats, a, a.Y);
   hipLaunchKernelGGL(loss_sums_kernel, dim3(1), dim3(1024), 0, st, a.Y, target, mask, nY, scal);
@@ -354,15 +391,69 @@ extern "C" gmgm_status gmgm_ws_train_step(gmgm_ctx_t c, float* params, float* ad
   hipLaunchKernelGGL(colsum_kernel, dim3(nb(D_H)), dim3(256), 0, st, dZ, B, D_H, g + OFF_B1);
   if (grad_out)
     GMGM_HIP(c, hipMemcpyAsync(grad_out, g, N_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, st));
-  const float bc1 = (float)(1.0 - std::pow(0.9, (double)step));
-  const float bc2 = (float)(1.0 - std::pow(0.999, (double)step));
+  float bc1 = 1.0f, bc2 = 1.0f;
+  if (state) {
+    hipLaunchKernelGGL(adam_count_kernel, dim3(1), dim3(1), 0, st, state, bcp);
+  } else {
+    bc1 = (float)(1.0 - std::pow(0.9, (double)step));
+    bc2 = (float)(1.0 - std::pow(0.999, (double)step));
+  }
   hipLaunchKernelGGL(adamw_kernel, dim3(nb(N_PARAMS)), dim3(256), 0, st, params, adam_m, adam_v, g, N_PARAMS, lr,
-                     weight_decay, bc1, bc2);
+                     weight_decay, bc1, bc2, state ? (const float*)bcp : (const float*)nullptr);
   if (loss_out) {
     GMGM_HIP(c, hipMemcpyAsync(loss_out, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
     GMGM_HIP(c, hipStreamSynchronize(st));
   }
   GMGM_HIP(c, hipGetLastError());
+  return GMGM_OK;
+}
+}  // namespace gmgm_ws
+
+extern "C" gmgm_status gmgm_ws_train_step(gmgm_ctx_t c, float* params, float* adam_m, float* adam_v, int64_t step,
+                                          int32_t batch, const float* feats, const float* target, const float* mask,
+                                          float lr, float weight_decay, double* loss_out, float* grad_out) {
+  GMGM_CHECK_CTX(c);
+  if (!params || !adam_m || !adam_v || !feats || !target) return set_err(c, GMGM_E_ARG, "null pointer argument");
+  if (batch < 1 || batch > MAX_BATCH) return set_err(c, GMGM_E_SHAPE, "batch must be in [1, %d]", MAX_BATCH);
+  if (step < 1 || !(lr >= 0) || !(weight_decay >= 0))
+    return set_err(c, GMGM_E_ARG, "need step >= 1, lr >= 0, weight_decay >= 0");
+  GMGM_HIP(c, hipSetDevice(c->device));
+  return train_impl(c, params, adam_m, adam_v, step, weight_decay, nullptr, batch, feats, target, mask, lr,
+                    loss_out, grad_out);
+}
+
+extern "C" int64_t gmgm_warmstart_state_bytes(void) { return OPT_BYTES; }
+
+extern "C" gmgm_status gmgm_warmstart_state_init(gmgm_ctx_t c, void* opt_state, float weight_decay) {
+  GMGM_CHECK_CTX(c);
+  if (!opt_state) return set_err(c, GMGM_E_ARG, "null pointer argument");
+  if (!(weight_decay >= 0) || !std::isfinite(weight_decay))
+    return set_err(c, GMGM_E_ARG, "weight_decay must be finite and >= 0");
+  GMGM_HIP(c, hipSetDevice(c->device));
+  hipLaunchKernelGGL(opt_init_kernel, dim3(nb(2 * N_PARAMS)), dim3(256), 0, c->stream, (char*)opt_state,
+                     weight_decay);
+  GMGM_HIP(c, hipGetLastError());
+  return GMGM_OK;
+}
+
+extern "C" gmgm_status gmgm_warmstart_infer(gmgm_ctx_t c, const void* weights, int32_t batch, const float* feats,
+                                            float* out) {
+  return gmgm_ws_forward(c, (const float*)weights, batch, feats, out);
+}
+
+extern "C" gmgm_status gmgm_warmstart_train_step(gmgm_ctx_t c, void* weights, void* opt_state, int32_t batch,
+                                                 const float* feats, const float* target, const float* mask,
+                                                 float lr, float* loss_out) {
+  GMGM_CHECK_CTX(c);
+  if (!weights || !opt_state || !feats || !target) return set_err(c, GMGM_E_ARG, "null pointer argument");
+  if (batch < 1 || batch > MAX_BATCH) return set_err(c, GMGM_E_SHAPE, "batch must be in [1, %d]", MAX_BATCH);
+  if (!(lr >= 0) || !std::isfinite(lr)) return set_err(c, GMGM_E_ARG, "lr must be finite and >= 0");
+  GMGM_HIP(c, hipSetDevice(c->device));
+  char* stt = (char*)opt_state;
+  double loss = 0.0;
+  GMGM_TRY(train_impl(c, (float*)weights, (float*)(stt + OPT_M), (float*)(stt + OPT_V), 0, 0.0f,
+                      (OptHeader*)stt, batch, feats, target, mask, lr, loss_out ? &loss : nullptr, nullptr));
+  if (loss_out) *loss_out = (float)loss;
   return GMGM_OK;
 }
 

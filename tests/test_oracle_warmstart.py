@@ -3,6 +3,7 @@ against closed forms and finite differences -- no GPU."""
 import math
 
 import numpy as np
+import pytest
 
 from oracle import warmstart as W
 
@@ -110,3 +111,41 @@ def test_adamw_first_step_closed_form():
 
 def test_parameter_count():
     assert W.N_PARAMS == 1028 * 256 + 256 + 256 * 256 + 256 + 1024 * 256 + 1024 == 592384
+
+
+@pytest.mark.parametrize("wd", [0.0, 1e-2])
+def test_adamw_constant_gradient_every_step(wd):
+    """A constant gradient g: m_t = (1 - 0.9^t) g and v_t = (1 - 0.999^t) g^2, so
+    the bias-corrected moments are g and g^2 at every step t and each update is
+    lr (g / (|g| + eps) + wd theta); a wrong correction at any t > 1 breaks it."""
+    rng = np.random.default_rng(6)
+    theta0 = rng.standard_normal(40)
+    g = rng.standard_normal(40)
+    lr = 1e-3
+    theta, m, v = theta0.copy(), np.zeros(40), np.zeros(40)
+    want = theta0.copy()
+    for t in range(1, 8):
+        theta, m, v = W.adamw_step(theta, m, v, g, t, lr, wd)
+        want = want - lr * (g / (np.abs(g) + 1e-8) + wd * want)
+        np.testing.assert_allclose(m, (1 - 0.9 ** t) * g, rtol=1e-12)
+        np.testing.assert_allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12)
+        np.testing.assert_allclose(theta, want, rtol=1e-12, atol=1e-15)
+
+
+def test_adamw_alternating_gradient_closed_form():
+    """g_t = (-1)^(t+1) g: m_t = 0.1 g (-1)^(t+1) (1 - (-0.9)^t) / 1.9 (a geometric
+    sum), v_t = (1 - 0.999^t) g^2; the update uses m_t / (1 - 0.9^t) and |g|."""
+    rng = np.random.default_rng(7)
+    theta0 = rng.standard_normal(30)
+    g = rng.standard_normal(30)
+    lr, wd = 2e-3, 0.0
+    theta, m, v = theta0.copy(), np.zeros(30), np.zeros(30)
+    want = theta0.copy()
+    for t in range(1, 7):
+        gt = g if t % 2 == 1 else -g
+        theta, m, v = W.adamw_step(theta, m, v, gt, t, lr, wd)
+        m_t = 0.1 * g * (-1) ** (t + 1) * (1 - (-0.9) ** t) / 1.9
+        np.testing.assert_allclose(m, m_t, rtol=1e-12, atol=1e-15)
+        mh = m_t / (1 - 0.9 ** t)
+        want = want - lr * mh / (np.abs(g) + 1e-8)
+        np.testing.assert_allclose(theta, want, rtol=1e-12, atol=1e-15)

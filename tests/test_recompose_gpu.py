@@ -178,3 +178,25 @@ def _full_V():
     if "V" not in _FULL:
         _FULL["V"] = synth.cell_factor_proxy(1_000_000, 100, 40, seed=3000)
     return _FULL["V"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("k", [1, 10])
+def test_aligned_rounding_rows_reach_the_fallbacks(lib, prec, k):
+    """Rows built so that operand rounding puts a true top-k column below 32
+    decoys (tests/_adversarial.py): the result must still equal the oracle's,
+    the low-precision certificate must send the row to the FP32 re-sweep, and a
+    row whose top values are 40 exact ties must reach the exact scan."""
+    from tests import _adversarial
+    A = _adversarial.aligned_rounding_rows("fp8" if prec == "fp8" else "bf16", k=k)
+    V, psi = A["V"], A["psi"]
+    n = V.shape[0]
+    rp, col, val, st = _run(lib, V, psi, k, prec, cand_cap=32)
+    _check(V, psi, k, np.arange(n), rp, col, val, f"{prec} adversarial k={k}")
+    col = col.reshape(n, k)
+    assert A["hidden"] in col[A["row"]]
+    # the tie row is a near tie by construction; the exact scan still resolves
+    # ties to the smaller column, as the oracle does
+    assert list(col[A["tie_row"]]) == A["tie_cols"][:k]
+    assert st["rows_fallback"] >= 2, st
+    assert st["rows_exact"] >= 1, st

@@ -202,3 +202,20 @@ def test_full_size_one_million_cells_sampled(lib):
     same_row = ri[1:] == ri[:-1]
     assert np.all(col[1:][same_row] > col[:-1][same_row])          # ascending within rows
     print("threshold", thr, "nnz", out.nnz, flush=True)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_aligned_rounding_rows_keep_the_hidden_entry(lib, prec):
+    """A threshold between a row's true largest |Psi_ij| and everything else,
+    on inputs whose operand rounding pulls that entry furthest below it
+    (tests/_adversarial.py): the entry must still be kept, as in the oracle."""
+    from tests import _adversarial
+    A = _adversarial.aligned_rounding_rows("fp8" if prec == "fp8" else "bf16", k=1)
+    V, psi, thr = A["V"], A["psi"], A["thr"]
+    n = V.shape[0]
+    rp, col, val, nnz = _run(lib, V, psi, thr, prec)
+    _check(V, psi, thr, np.arange(n), rp, col, val, f"{prec} adversarial")
+    i, h = A["row"], A["hidden"]
+    assert list(col[rp[i]:rp[i + 1]]) == [h]
+    assert list(col[rp[h]:rp[h + 1]]) == [i]
+    assert nnz == 2

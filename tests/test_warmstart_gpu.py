@@ -98,6 +98,52 @@ def test_gradient_and_adamw_step_parity(lib, batch, masked):
     np.testing.assert_allclose(m.cpu().numpy(), m_ref, rtol=1e-3, atol=1e-4 * np.max(np.abs(m_ref)))
 
 
+def test_three_adamw_steps_parity_both_entry_points(lib):
+    """Three consecutive steps (bias corrections past the first) through
+    gmgm_ws_train_step (host update count) and gmgm_warmstart_train_step
+    (update count in the device state): both give the same parameters, and
+    they follow the oracle's FP64 trajectory wherever the gradient's sign is
+    well determined at every step."""
+    import torch
+    theta, X, T, M = _net(321, 48)
+    n = lib.ws_param_count()
+    lr, wd = 1e-3, 1e-2
+    p1 = _d(theta)
+    m1 = torch.zeros(n, dtype=torch.float32, device="cuda")
+    v1 = torch.zeros(n, dtype=torch.float32, device="cuda")
+    p2 = _d(theta)
+    st = lib.warmstart_state(weight_decay=wd)
+    th, mr, vr = theta.astype(np.float64), np.zeros(n), np.zeros(n)
+    sure = np.ones(n, bool)
+    for t in range(1, 4):
+        l1 = lib.ws_train_step(p1, m1, v1, t, _d(X), _d(T), _d(M), lr, wd)
+        l2 = lib.warmstart_train_step(p2, st, _d(X), _d(T), _d(M), lr)
+        L, g = W.loss_and_grad(th, X.astype(np.float64), T.astype(np.float64), M.astype(np.float64))
+        assert abs(l1 - L) <= 1e-5 * L and abs(l2 - L) <= 1e-5 * L
+        offs = np.cumsum([0] + [int(np.prod(s)) for _, s in W.SHAPES])
+        for lo, hi in zip(offs[:-1], offs[1:]):
+            sure[lo:hi] &= np.abs(g[lo:hi]) > 1e-2 * np.max(np.abs(g[lo:hi]))
+        th, mr, vr = W.adamw_step(th, mr, vr, g, t, lr, wd)
+    a, b = p1.cpu().numpy(), p2.cpu().numpy()
+    assert np.array_equal(a, b)
+    assert int(st[:8].cpu().numpy().view(np.int64)[0]) == 3
+    assert sure.mean() > 0.5
+    assert np.all(np.abs(a - th)[sure] <= 3e-3 * lr)
+    assert np.all(np.abs(a - th) <= 6.3 * lr)
+    np.testing.assert_allclose(m1.cpu().numpy()[sure], mr[sure], rtol=1e-3)
+    ms = st[256:256 + 4 * n].view(torch.float32).cpu().numpy()
+    np.testing.assert_array_equal(ms, m1.cpu().numpy())
+
+
+def test_warmstart_infer_equals_forward(lib):
+    theta, X, _, _ = _net(77, 19)
+    a = lib.ws_forward(_d(theta), _d(X)).cpu().numpy()
+    b = lib.warmstart_infer(_d(theta), _d(X)).cpu().numpy()
+    Yr = W.forward(theta.astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(b - Yr)) <= 1e-4 * np.max(np.abs(Yr))
+    np.testing.assert_array_equal(a, b)
+
+
 def test_training_is_deterministic(lib):
     import torch
     theta, X, T, M = _net(7, 64)
