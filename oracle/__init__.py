@@ -20,7 +20,7 @@ of the function that takes them.
 """
 from .gram import gram_dense, gram_csr
 from .spectral import eigh_desc, numerical_rank, cell_factor
-from .solver import Problem, nll, grad, solve_eigs, alg1_gradient_descent, default_eps
+from .solver import Problem, nll, grad, solve_eigs, projected_gradient, default_eps
 from .recompose import psi_dense, psi_rows, psi_blockwise
 from .topk import topk_row, topk_csr, near_tie_rows
 from . import warmstart
@@ -31,7 +31,7 @@ from . import solver_tensor
 
 __all__ = [
     "gram_dense", "gram_csr", "eigh_desc", "numerical_rank", "cell_factor",
-    "Problem", "nll", "grad", "solve_eigs", "alg1_gradient_descent", "default_eps",
+    "Problem", "nll", "grad", "solve_eigs", "projected_gradient", "default_eps",
     "psi_dense", "psi_rows", "psi_blockwise", "topk_row", "topk_csr", "near_tie_rows",
     "warmstart", "range_finder", "significance", "skeptic", "solver_tensor",
 ]

@@ -34,12 +34,23 @@ Readings taken here (the paper leaves these open):
   free coordinate contributes |g_i| / (E_i / 2) and a coordinate at its bound
   contributes max(0, -g_i) / (E_i / 2).
 
-Method: projected Newton for bound constraints (Bertsekas 1982) with a
-Levenberg-Marquardt damping that vanishes at the solution, an Armijo search
-along the projection arc, Newton systems solved by a Schur complement that
-eliminates an independent set of axes (whose Hessian blocks are diagonal).
-``alg1_gradient_descent`` is the literal gradient descent of Algorithm 1 for
-small cross-checks.
+Method (an optimiser of its own, sharing no step rule with the library):
+profile likelihood.  The axes are split into an outer set and an inner set
+that no modality joins to itself (an independent set of the modality graph).
+For fixed outer eigenvalues the NLL separates into one-dimensional convex
+problems, one per inner eigenvalue: lambda_m,j solves
+E_m,j = sum_{partners} sum_i 1/(lambda_l,i + lambda_m,j), or sits at eps_m
+when the derivative is already non-negative there; each is solved to the last
+bit by Newton's method from the left (the right-hand side is convex and
+decreasing).  The profiled NLL of the outer eigenvalues is convex; its
+gradient is the partial gradient at the inner optimum (envelope theorem) and
+its Hessian the Schur complement of the free inner coordinates.  It is
+minimised by ``oracle.newton.minimize_box`` (Bertsekas' projected Newton).
+Sums over the partner axis are taken in extended precision, so the scaled KKT
+residual reaches ~1e-15.  The result is finally moved along the flat
+directions to the start's gauge (the rule above).
+``projected_gradient`` is a plain projected gradient descent of the same NLL
+from Algorithm 1's start, for small cross-checks.
 """
 from __future__ import annotations
 
@@ -47,6 +58,8 @@ import math
 from dataclasses import dataclass, field
 
 import numpy as np
+
+from .newton import minimize_box
 
 
 @dataclass
@@ -127,74 +140,6 @@ def hess_dense(lam, prob: Problem):
         H[off[a]:off[a + 1], off[b]:off[b + 1]] += C
         H[off[b]:off[b + 1], off[a]:off[a + 1]] += C.T
     return H
-
-
-def _hub_axes(prob: Problem):
-    """Minimum-size vertex cover of the modality graph; the rest is an independent set."""
-    L = prob.n_axes
-    best = None
-    for mask in range(1 << L):
-        K = [l for l in range(L) if mask >> l & 1]
-        if all(a in K or b in K for a, b in prob.modalities):
-            w = sum(prob.ranks[l] for l in K)
-            if best is None or w < best[0]:
-                best = (w, K)
-    return best[1]
-
-
-def newton_direction(lam, g, free, prob: Problem, rho: float):
-    """Solve (H_FF + rho diag(H_FF)) d_F = -g_F by a Schur complement on the hub axes."""
-    diag, cross = hess_parts(lam, prob)
-    K = _hub_axes(prob)
-    leaves = [l for l in range(prob.n_axes) if l not in K]
-    fidx = [np.nonzero(f)[0] for f in free]
-    dd = [d * (1.0 + rho) for d in diag]
-    # hub system over free hub coordinates
-    koff = np.concatenate([[0], np.cumsum([fidx[l].size for l in K])])
-    nk = int(koff[-1])
-    S = np.zeros((nk, nk))
-    rhs = np.zeros(nk)
-    pos = {l: t for t, l in enumerate(K)}
-    for t, l in enumerate(K):
-        sl = slice(koff[t], koff[t + 1])
-        S[sl, sl] += np.diag(dd[l][fidx[l]])
-        rhs[sl] = -g[l][fidx[l]]
-
-    def block(a, b):  # cross block rows of axis a, cols of axis b (free coords only)
-        if (a, b) in cross:
-            C = cross[(a, b)]
-        else:
-            C = cross[(b, a)].T
-        return C[np.ix_(fidx[a], fidx[b])]
-
-    for (a, b) in cross:
-        if a in pos and b in pos:
-            C = block(a, b)
-            S[koff[pos[a]]:koff[pos[a] + 1], koff[pos[b]]:koff[pos[b] + 1]] += C
-            S[koff[pos[b]]:koff[pos[b] + 1], koff[pos[a]]:koff[pos[a] + 1]] += C.T
-    for m in leaves:
-        Dm = dd[m][fidx[m]]
-        gm = -g[m][fidx[m]]
-        partners = [l for l in K if (l, m) in cross or (m, l) in cross]
-        Bs = {l: block(l, m) for l in partners}
-        for l in partners:
-            sl = slice(koff[pos[l]], koff[pos[l] + 1])
-            rhs[sl] -= Bs[l] @ (gm / Dm)
-            for l2 in partners:
-                sl2 = slice(koff[pos[l2]], koff[pos[l2] + 1])
-                S[sl, sl2] -= (Bs[l] / Dm[None, :]) @ Bs[l2].T
-    dK = np.linalg.solve(S, rhs) if nk else np.zeros(0)
-    d = [np.zeros_like(e) for e in prob.E]
-    for t, l in enumerate(K):
-        d[l][fidx[l]] = dK[koff[t]:koff[t + 1]]
-    for m in leaves:
-        Dm = dd[m][fidx[m]]
-        acc = -g[m][fidx[m]].copy()
-        for l in K:
-            if (l, m) in cross or (m, l) in cross:
-                acc -= block(l, m).T @ d[l][fidx[l]]
-        d[m][fidx[m]] = acc / Dm
-    return d
 
 
 def flat_shift_space(axis_sets, ranks, traces, rel_tol: float = 1e-12):
@@ -327,87 +272,173 @@ class SolveResult:
     n_pinned: list
 
 
-STEP_SHRINK = 64.0
+def split_axes(prob: Problem):
+    """(outer, inner): inner is the independent set of the modality graph with the
+    largest total rank (enumerated; at most a few axes), outer the rest."""
+    L = prob.n_axes
+    best = None
+    for mask in range(1 << L):
+        inner = [l for l in range(L) if mask >> l & 1]
+        if any(a in inner and b in inner for a, b in prob.modalities):
+            continue
+        w = sum(prob.ranks[l] for l in inner)
+        if best is None or w > best[0]:
+            best = (w, inner)
+    inner = best[1]
+    return [l for l in range(L) if l not in inner], inner
 
 
-def solve_eigs(prob: Problem, warm=None, tol: float = 1e-12, max_iter: int = 200) -> SolveResult:
-    """Projected Newton from the cold start 1/E, or from a warm start (moved to the
-    gauge and clipped to the box) when its NLL is not above the cold start's.
+def _partners(prob: Problem, m):
+    return [a if b == m else b for a, b in prob.modalities if m in (a, b)]
 
-    The minimiser does not depend on the path.  Along flat directions the NLL is
-    constant: steps may drift along them, and the result is moved back to the
-    start's gauge at the end."""
-    flats = flat_directions(prob)
-    lam = cold_start(prob)
-    if warm is not None:
-        # a supplied start is used when it is at least as good as 1/E
-        w = _fix_gauge([np.asarray(x, dtype=np.float64).copy() for x in warm], prob, flats)
-        w = [np.maximum(l, eps) for l, eps in zip(w, prob.eps)]
-        if nll(w, prob) <= nll(lam, prob):
-            lam = w
-    eps = prob.eps
-    it = 0
-    g = grad(lam, prob)
-    kkt = kkt_residual(lam, g, prob)
-    for _round in range(3):
-        stalled = False
-        while kkt > tol and it < max_iter:
-            it += 1
-            f0 = nll(lam, prob)
-            diag, _ = hess_parts(lam, prob)
-            # coordinates within a diagonal-Newton step of their bound that want to go down
-            active = []
-            for l in range(prob.n_axes):
-                reach = np.minimum(1e-3 * lam[l], g[l] / diag[l])
-                active.append((lam[l] - eps[l] <= reach) & (g[l] > 0))
-            free = [~a for a in active]
-            rho = min(1e-2, kkt)
-            d = newton_direction(lam, g, free, prob, rho)
-            for l in range(prob.n_axes):
-                d[l][active[l]] = -g[l][active[l]] / diag[l][active[l]]
-            # floor of the step: an active coordinate may go to its bound, a free one
-            # may shrink by at most STEP_SHRINK per iteration (a coupled Newton step
-            # can overshoot far below the optimum, and recovery from the bound
-            # doubles the value per iteration at best)
-            floor = [np.where(active[l], eps[l], np.maximum(eps[l], lam[l] / STEP_SHRINK))
-                     for l in range(prob.n_axes)]
-            alpha = 1.0
-            accepted = False
-            for _ in range(60):
-                trial = [np.maximum(lam[l] + alpha * d[l], floor[l]) for l in range(prob.n_axes)]
-                pred = 0.0
-                for l in range(prob.n_axes):
-                    pred += alpha * float(np.dot(g[l][free[l]], d[l][free[l]]))
-                    pred += float(np.dot(g[l][active[l]], trial[l][active[l]] - lam[l][active[l]]))
-                f1 = nll(trial, prob)
-                if f1 <= f0 + 1e-4 * pred or abs(pred) <= 1e-13 * (abs(f0) + 1.0):
-                    accepted = True
-                    break
-                alpha *= 0.5
-            if not accepted:
-                stalled = True
-                break
-            lam = trial
-            g = grad(lam, prob)
-            kkt = kkt_residual(lam, g, prob)
-        # back to the start's gauge along the flat directions; resume if that
-        # moved the point off the tolerance (rounding of the shift, the box)
-        lam = [np.maximum(l, e) for l, e in zip(_fix_gauge(lam, prob, flats), eps)]
-        g = grad(lam, prob)
-        kkt = kkt_residual(lam, g, prob)
-        if kkt <= tol or it >= max_iter or stalled or not flats:
+
+def inner_solve(lam_partners, E, eps, x0=None):
+    """Minimisers x_j >= eps of 1/2 [E_j x - sum_i log(p_i + x)] for every j:
+    the root of phi_j(x) = sum_i 1/(p_i + x) - E_j (convex and decreasing in x),
+    or eps where phi_j(eps) <= 0.  Newton's method from a point left of the
+    root converges monotonically from the left; a start x0 right of the root
+    lands left of it after one step (the tangent of a convex function lies
+    below it), and a step below eps restarts at eps."""
+    p = np.asarray(lam_partners, dtype=np.longdouble)[:, None]
+    E = np.asarray(E, dtype=np.longdouble)
+    x = np.full(E.shape, eps, dtype=np.longdouble) if x0 is None else np.maximum(
+        np.asarray(x0, dtype=np.longdouble), eps)
+
+    def phi(x, sel):
+        t = 1.0 / (p + x[None, :])
+        return t.sum(axis=0) - E[sel], (t * t).sum(axis=0)
+
+    allj = np.ones(E.shape, dtype=bool)
+    v, dv = phi(np.full(E.shape, eps, dtype=np.longdouble), allj)
+    pinned = v <= 0
+    x[pinned] = eps
+    # the iterations in FP64 (the same monotone Newton), then in extended
+    # precision until the step is below its rounding
+    p64, E64 = np.asarray(p, np.float64), np.asarray(E, np.float64)
+    x64 = np.asarray(x, np.float64)
+    todo = ~pinned
+    for _ in range(400):
+        if not todo.any():
             break
-    pinned = [int(np.sum(l <= e * (1 + 1e-12))) for l, e in zip(lam, eps)]
-    return SolveResult(lam, it, kkt, kkt <= tol, pinned)
+        t = 1.0 / (p64 + x64[todo][None, :])
+        xn = x64[todo] + (t.sum(axis=0) - E64[todo]) / (t * t).sum(axis=0)
+        xn = np.where(xn < eps, eps, xn)
+        done = np.abs(xn - x64[todo]) <= 1e-13 * xn
+        x64[todo] = xn
+        idx = np.flatnonzero(todo)
+        todo[idx[done]] = False
+    x = np.asarray(x64, dtype=np.longdouble)
+    todo = ~pinned
+    for _ in range(50):
+        if not todo.any():
+            break
+        v, dv = phi(x[todo], todo)
+        step = v / dv                       # Newton: x - phi / phi' with phi' = -dv
+        xn = x[todo] + step
+        xn = np.where(xn < eps, eps, xn)
+        done = np.abs(xn - x[todo]) <= 4 * np.finfo(np.longdouble).eps * xn
+        x[todo] = xn
+        idx = np.flatnonzero(todo)
+        todo[idx[done]] = False
+    return np.asarray(x, dtype=np.float64), pinned
 
 
-def alg1_gradient_descent(prob: Problem, tol: float = 1e-9, max_iter: int = 200_000):
-    """Algorithm 1 as printed: lambda^0 = 1/E, mu = 1, lambda <- lambda - mu * grad,
-    with mu halved while some modality's sum of smallest eigenvalues is below the
-    sum of its eps, or while the step would not lower the NLL ("decrease mu if
-    needed").  For small cross-checks only."""
-    lam = [1.0 / e for e in prob.E]
-    mu = 1.0
+def _sum_inv(lam_a, lam_b, axis):
+    """sum over the other axis of 1/(lam_a,i + lam_b,j), in extended precision."""
+    t = 1.0 / (np.asarray(lam_a, np.longdouble)[:, None] + np.asarray(lam_b, np.longdouble)[None, :])
+    return np.asarray(t.sum(axis=axis), dtype=np.float64)
+
+
+def grad_precise(lam, prob: Problem):
+    """The gradient of the NLL with the pair sums in extended precision."""
+    g = [0.5 * e.copy() for e in prob.E]
+    for a, b in prob.modalities:
+        g[a] -= 0.5 * _sum_inv(lam[a], lam[b], 1)
+        g[b] -= 0.5 * _sum_inv(lam[a], lam[b], 0)
+    return g
+
+
+def _profile(prob: Problem, outer, inner):
+    """evaluate(x, need_derivs) of the profiled NLL over the outer eigenvalues
+    (concatenated), for oracle.newton.minimize_box; the last inner solution is
+    kept in state["lam"] and reused as the next start."""
+    off = np.concatenate([[0], np.cumsum([prob.ranks[l] for l in outer])])
+    state = {"inner": {m: None for m in inner}, "lam": None}
+
+    def full(x):
+        lam = [None] * prob.n_axes
+        for t, l in enumerate(outer):
+            lam[l] = x[off[t]:off[t + 1]]
+        pins = {}
+        for m in inner:
+            parts = np.concatenate([lam[l] for l in _partners(prob, m)])
+            lam[m], pins[m] = inner_solve(parts, prob.E[m], prob.eps[m], state["inner"][m])
+            state["inner"][m] = lam[m]
+        return lam, pins
+
+    def evaluate(x, need):
+        lam, pins = full(x)
+        state["lam"] = lam
+        f = nll(lam, prob)
+        if not need:
+            return f
+        g = grad_precise(lam, prob)
+        gx = np.concatenate([g[l] for l in outer])
+        diag, cross = hess_parts(lam, prob)
+        n = int(off[-1])
+        H = np.zeros((n, n))
+        pos = {l: t for t, l in enumerate(outer)}
+        for t, l in enumerate(outer):
+            H[off[t]:off[t + 1], off[t]:off[t + 1]] += np.diag(diag[l])
+        for (a, b), C in cross.items():
+            if a in pos and b in pos:
+                H[off[pos[a]]:off[pos[a] + 1], off[pos[b]]:off[pos[b] + 1]] += C
+                H[off[pos[b]]:off[pos[b] + 1], off[pos[a]]:off[pos[a] + 1]] += C.T
+        # Schur complement of the free inner coordinates (their Hessian block is diagonal)
+        for m in inner:
+            free = ~pins[m]
+            B = np.zeros((n, int(free.sum())))
+            for (a, b), C in cross.items():
+                if b == m and a in pos:
+                    B[off[pos[a]]:off[pos[a] + 1]] += C[:, free]
+                elif a == m and b in pos:
+                    B[off[pos[b]]:off[pos[b] + 1]] += C[free, :].T
+            H -= (B / diag[m][free][None, :]) @ B.T
+        return f, gx, H
+
+    return evaluate, off, state
+
+
+def solve_eigs(prob: Problem, warm=None, tol: float = 1e-15, max_iter: int = 500) -> SolveResult:
+    """The minimiser over the box (profile likelihood, see the module header),
+    started from Algorithm 1's 1/E or from ``warm`` (moved to the gauge and
+    clipped to the box), then moved to the start's gauge."""
+    flats = flat_directions(prob)
+    lam0 = cold_start(prob)
+    if warm is not None:
+        w = _fix_gauge([np.asarray(x, dtype=np.float64).copy() for x in warm], prob, flats)
+        lam0 = [np.maximum(l, eps) for l, eps in zip(w, prob.eps)]
+    outer, inner = split_axes(prob)
+    evaluate, off, state = _profile(prob, outer, inner)
+    x0 = np.concatenate([lam0[l] for l in outer])
+    lo = np.concatenate([np.full(prob.ranks[l], prob.eps[l]) for l in outer])
+    scale = np.concatenate([0.5 * prob.E[l] for l in outer])
+    x, it, _, _ = minimize_box(evaluate, x0, lo, scale, tol, max_iter)
+    evaluate(x, False)
+    lam = [np.array(l, dtype=np.float64) for l in state["lam"]]
+    lam = [np.maximum(l, e) for l, e in zip(_fix_gauge(lam, prob, flats), prob.eps)]
+    kkt = kkt_residual(lam, grad_precise(lam, prob), prob)
+    pinned = [int(np.sum(l <= e * (1 + 1e-12))) for l, e in zip(lam, prob.eps)]
+    return SolveResult(lam, it, kkt, kkt <= max(tol, 1e-14), pinned)
+
+
+def projected_gradient(prob: Problem, tol: float = 1e-9, max_iter: int = 200_000):
+    """Projected gradient descent of the NLL over the box from Algorithm 1's start
+    1/E: lambda <- max(lambda - t g, eps), the step t grown by 2 after an accepted
+    step and cut by 4 until the NLL decreases by at least a tenth of the
+    first-order prediction along the projected move.  Slow; small cross-checks."""
+    lam = cold_start(prob)
+    t = 1.0
     it = 0
     while it < max_iter:
         g = grad(lam, prob)
@@ -415,14 +446,14 @@ def alg1_gradient_descent(prob: Problem, tol: float = 1e-9, max_iter: int = 200_
             break
         f0 = nll(lam, prob)
         while True:
-            trial = [l - mu * gl for l, gl in zip(lam, g)]
-            ok = all(trial[a].min() + trial[b].min() >= prob.eps[a] + prob.eps[b]
-                     for a, b in prob.modalities)
-            if ok and nll(trial, prob) < f0:
+            trial = [np.maximum(l - t * gl, e) for l, gl, e in zip(lam, g, prob.eps)]
+            move = sum(float(np.dot(gl, tl - l)) for gl, tl, l in zip(g, trial, lam))
+            if nll(trial, prob) <= f0 + 0.1 * move:
                 break
-            mu *= 0.5
-            if mu < 1e-300:
+            t *= 0.25
+            if t < 1e-300:
                 return lam, it
         lam = trial
+        t *= 2.0
         it += 1
     return lam, it

@@ -18,12 +18,12 @@ every two axes of a modality, the cross block sum over the remaining axes of
 1/2 s^-2.  Two-axis modalities reduce this to the pair model of
 ``oracle.solver``.
 
-Method, readings and stopping rule as ``oracle.solver`` (box lambda >= eps,
-scaled KKT, projected Newton with LM damping rho = min(1e-2, KKT), Armijo
-along the projection arc, a shrink limit of STEP_SHRINK per step for free
-coordinates, the start's gauge restored along flat directions), with the
-Newton system solved densely (the Schur complement of the pair solver needs
-diagonal leaf blocks, which axes of a three-axis modality do not have).
+Readings and stopping rule as ``oracle.solver`` (box lambda >= eps, scaled
+KKT, the start's gauge restored along flat directions).  Method: the whole
+problem as one dense projected Newton (``oracle.newton.minimize_box``:
+Bertsekas' active set and projection-arc search, a Levenberg-Marquardt term
+proportional to the gradient), with the gradient's tuple sums taken in
+extended precision so that the scaled KKT residual reaches ~1e-15.
 """
 from __future__ import annotations
 
@@ -32,9 +32,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from .newton import minimize_box
 from .solver import default_eps, flat_shift_space, nearest_feasible_shift
-
-STEP_SHRINK = 64.0
 
 
 @dataclass
@@ -148,64 +147,42 @@ class SolveResult:
     n_pinned: list
 
 
-def solve_eigs(prob: TensorProblem, tol: float = 1e-12, max_iter: int = 200) -> SolveResult:
-    """Projected Newton from the cold start 1/E (the steps of oracle.solver with a
-    dense Newton system)."""
+def grad_precise(lam, prob: TensorProblem):
+    """The gradient with the tuple sums in extended precision."""
+    g = [0.5 * e.copy() for e in prob.E]
+    for m in prob.modalities:
+        inv = 1.0 / _sums([np.asarray(x, np.longdouble) for x in lam], m)
+        for t, a in enumerate(m):
+            g[a] -= np.asarray(0.5 * inv.sum(axis=tuple(u for u in range(len(m)) if u != t)), np.float64)
+    return g
+
+
+def solve_eigs(prob: TensorProblem, warm=None, tol: float = 1e-15, max_iter: int = 500) -> SolveResult:
+    """The minimiser over the box by one dense projected Newton (see the module
+    header) from the cold start 1/E or ``warm`` (moved to the gauge and clipped),
+    then moved to the start's gauge."""
     flats = flat_directions(prob)
-    lam = cold_start(prob)
-    eps = prob.eps
-    L = prob.n_axes
+    lam0 = cold_start(prob)
+    if warm is not None:
+        w = _fix_gauge([np.asarray(x, dtype=np.float64).copy() for x in warm], prob, flats)
+        lam0 = [np.maximum(l, e) for l, e in zip(w, prob.eps)]
     off = np.concatenate([[0], np.cumsum(prob.ranks)])
-    it = 0
-    g = grad(lam, prob)
-    kkt = kkt_residual(lam, g, prob)
-    for _round in range(3):
-        stalled = False
-        while kkt > tol and it < max_iter:
-            it += 1
-            f0 = nll(lam, prob)
-            H = hess_dense(lam, prob)
-            diag = [np.diag(H)[off[l]:off[l + 1]].copy() for l in range(L)]
-            active = []
-            for l in range(L):
-                reach = np.minimum(1e-3 * lam[l], g[l] / diag[l])
-                active.append((lam[l] - eps[l] <= reach) & (g[l] > 0))
-            free = [~a for a in active]
-            rho = min(1e-2, kkt)
-            F = np.concatenate(free)
-            gall = np.concatenate(g)
-            A = H[np.ix_(F, F)].copy()
-            A[np.diag_indices_from(A)] *= 1.0 + rho
-            dF = np.linalg.solve(A, -gall[F])
-            dall = np.zeros(off[-1])
-            dall[F] = dF
-            d = [dall[off[l]:off[l + 1]].copy() for l in range(L)]
-            for l in range(L):
-                d[l][active[l]] = -g[l][active[l]] / diag[l][active[l]]
-            floor = [np.where(active[l], eps[l], np.maximum(eps[l], lam[l] / STEP_SHRINK)) for l in range(L)]
-            alpha = 1.0
-            accepted = False
-            for _ in range(60):
-                trial = [np.maximum(lam[l] + alpha * d[l], floor[l]) for l in range(L)]
-                pred = 0.0
-                for l in range(L):
-                    pred += alpha * float(np.dot(g[l][free[l]], d[l][free[l]]))
-                    pred += float(np.dot(g[l][active[l]], trial[l][active[l]] - lam[l][active[l]]))
-                f1 = nll(trial, prob)
-                if f1 <= f0 + 1e-4 * pred or abs(pred) <= 1e-13 * (abs(f0) + 1.0):
-                    accepted = True
-                    break
-                alpha *= 0.5
-            if not accepted:
-                stalled = True
-                break
-            lam = trial
-            g = grad(lam, prob)
-            kkt = kkt_residual(lam, g, prob)
-        lam = [np.maximum(l, e) for l, e in zip(_fix_gauge(lam, prob, flats), eps)]
-        g = grad(lam, prob)
-        kkt = kkt_residual(lam, g, prob)
-        if kkt <= tol or it >= max_iter or stalled or not flats:
-            break
-    pinned = [int(np.sum(l <= e * (1 + 1e-12))) for l, e in zip(lam, eps)]
-    return SolveResult(lam, it, kkt, kkt <= tol, pinned)
+    L = prob.n_axes
+
+    def split(x):
+        return [x[off[l]:off[l + 1]] for l in range(L)]
+
+    def evaluate(x, need):
+        lam = split(x)
+        f = nll(lam, prob)
+        if not need:
+            return f
+        return f, np.concatenate(grad_precise(lam, prob)), hess_dense(lam, prob)
+
+    lo = np.concatenate([np.full(prob.ranks[l], prob.eps[l]) for l in range(L)])
+    scale = np.concatenate([0.5 * e for e in prob.E])
+    x, it, _, _ = minimize_box(evaluate, np.concatenate(lam0), lo, scale, tol, max_iter)
+    lam = [np.maximum(l, e) for l, e in zip(_fix_gauge([v.copy() for v in split(x)], prob, flats), prob.eps)]
+    kkt = kkt_residual(lam, grad_precise(lam, prob), prob)
+    pinned = [int(np.sum(l <= e * (1 + 1e-12))) for l, e in zip(lam, prob.eps)]
+    return SolveResult(lam, it, kkt, kkt <= max(tol, 1e-14), pinned)

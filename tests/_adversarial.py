@@ -17,8 +17,9 @@ ahead of h, although h's exact value is the largest.  The error on h is
 rounded operands lets a certificate accept the decoys.
 
 A second block on the remaining coordinates holds a row `tie_row` whose
-largest values are `n_tie` > cap identical columns (exact ties): no candidate
-list can certify it, so it reaches the exact scan of the whole row.
+largest values are `n_tie` identical columns (exact ties), more than the
+candidate lists of both half rows of an FP32 sweep hold (2 x 32): no list can
+certify it, so it reaches the exact scan of the whole row.
 
 Every other row is small background noise.  Only inputs are built here.
 """
@@ -27,7 +28,7 @@ import numpy as np
 U = {"bf16": 2.0 ** -8, "fp8": 2.0 ** -4}
 
 
-def aligned_rounding_rows(prec="bf16", k=1, n=2048, r=100, cap=32, n_tie=40, seed=0):
+def aligned_rounding_rows(prec="bf16", k=1, n=2048, r=100, cap=32, n_tie=72, seed=0):
     u = U[prec]
     r1 = r // 2
     rng = np.random.default_rng(seed)

@@ -186,7 +186,7 @@ def test_aligned_rounding_rows_reach_the_fallbacks(lib, prec, k):
     """Rows built so that operand rounding puts a true top-k column below 32
     decoys (tests/_adversarial.py): the result must still equal the oracle's,
     the low-precision certificate must send the row to the FP32 re-sweep, and a
-    row whose top values are 40 exact ties must reach the exact scan."""
+    row whose top values are 72 exact ties must reach the exact scan."""
     from tests import _adversarial
     A = _adversarial.aligned_rounding_rows("fp8" if prec == "fp8" else "bf16", k=k)
     V, psi = A["V"], A["psi"]

@@ -240,3 +240,26 @@ def test_errors(lib):
     assert ei.value.status == 2
     lam, info = _gpu_solve(lib, E, [(0, 1, 2)])      # the context stays usable
     assert info["converged"]
+
+
+@pytest.mark.parametrize("which", ["coil10", "mixed"])
+def test_from_perturbed_starts_against_the_independent_minimiser(lib, which):
+    """Started 5% away from the oracle's minimiser (a dense projected Newton of
+    its own, KKT ~1e-15), the GPU reaches it within the bar."""
+    if which == "coil10":
+        E, mods = coil_like_spectra(seed=1)
+        E = [e[:10].copy() for e in E]
+    else:
+        E = low_rank_tensor_spectra((12, 9, 7), 3, seed=21)
+        rng0 = np.random.default_rng(22)
+        E = E + [np.sort(rng0.uniform(0.5, 30.0, r))[::-1].copy() for r in (5, 8, 6)]
+        mods = [(0, 1, 2), (0, 3), (0, 4, 5)]
+    prob = T.TensorProblem(E, mods)
+    ref = T.solve_eigs(prob)
+    assert ref.converged and ref.kkt <= 1e-14
+    rng = np.random.default_rng(32)
+    for t in range(2):
+        warm = [x * np.exp(0.05 * rng.standard_normal(x.size)) for x in ref.lam]
+        lam, info = _gpu_solve(lib, E, mods, warm=warm)
+        assert info["warm_used"]
+        _compare(prob, ref.lam, lam, info, f"{which} perturbed {t}")

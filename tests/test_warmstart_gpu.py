@@ -7,7 +7,8 @@ Bars: features, targets and apply within FP32 rounding of the FP64 values
 accumulation); the AdamW update within 1e-3 lr wherever the gradient's sign is
 well determined.  Gain: a network trained on cold solves of generated spectra
 starts held-out solves with fewer Newton iterations, and every warm solve ends
-within 1e-10 (relative, plus 1e-10 of the axis maximum) of the cold solve.
+within the solver's parity bar (1e-10 relative plus 1e-12 of the axis
+maximum) of the cold solve.
 """
 import numpy as np
 import pytest
@@ -130,7 +131,9 @@ def test_three_adamw_steps_parity_both_entry_points(lib):
     assert sure.mean() > 0.5
     assert np.all(np.abs(a - th)[sure] <= 3e-3 * lr)
     assert np.all(np.abs(a - th) <= 6.3 * lr)
-    np.testing.assert_allclose(m1.cpu().numpy()[sure], mr[sure], rtol=1e-3)
+    # first moments: sums of three gradients, each within the gradient bar (1e-4
+    # of the largest reference magnitude), so an absolute term of that size
+    np.testing.assert_allclose(m1.cpu().numpy()[sure], mr[sure], rtol=1e-3, atol=1e-4 * np.max(np.abs(mr)))
     ms = st[256:256 + 4 * n].view(torch.float32).cpu().numpy()
     np.testing.assert_array_equal(ms, m1.cpu().numpy())
 
@@ -193,6 +196,6 @@ def test_gain_warm_start_reduces_newton_iterations(lib):
         assert warm.info["converged"] and warm.info["n_pinned"] == cold.info["n_pinned"]
         for x, y in zip(warm.lam, cold.lam):
             x, y = x.cpu().numpy(), y.cpu().numpy()
-            assert np.all(np.abs(x - y) <= 1e-10 * (np.abs(y) + np.max(y)))
+            assert np.all(np.abs(x - y) <= 1e-10 * np.abs(y) + 1e-12 * np.max(y))
     print("cold", cold_it, "warm", warm_it, "loss", losses[0], losses[-1], flush=True)
     assert np.mean(warm_it) < np.mean(cold_it)
