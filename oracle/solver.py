@@ -228,11 +228,15 @@ def nearest_feasible_shift(t_star, flats, lam, eps, max_iter: int = 10_000):
             W.pop(int(np.argmax(size)))
             continue
         alpha, block = 1.0, -1
+        pn = float(np.linalg.norm(p))
         for l in range(L):
             if l in W:
                 continue
             ap = float(C[:, l] @ p)
-            if ap < 0.0:
+            # a normal in the span of the working set's (two axes whose
+            # coefficients are proportional in every flat direction) is
+            # orthogonal to p up to rounding: it cannot block
+            if ap < -1e-12 * float(np.linalg.norm(C[:, l])) * pn:
                 a_l = max(0.0, float(C[:, l] @ t - b[l])) / -ap     # slack / rate of its decrease
                 if a_l < alpha:
                     alpha, block = a_l, l
@@ -240,6 +244,18 @@ def nearest_feasible_shift(t_star, flats, lam, eps, max_iter: int = 10_000):
         if block >= 0:
             W.append(block)
     raise RuntimeError("gauge projection did not terminate")
+
+
+def snap_to_bound(lam, u, eps):
+    """lam_l + u_l per axis; a value the shift leaves within the rounding of the
+    addition above its bound is put on the bound (the exact shift puts it
+    there: the gauge projection is tight on that axis)."""
+    out = []
+    for l, x in enumerate(lam):
+        y = x + u[l]
+        tiny = 4 * np.finfo(float).eps * (np.abs(x) + abs(u[l]) + eps[l])
+        out.append(np.where(y - eps[l] <= tiny, eps[l], y))
+    return out
 
 
 def _fix_gauge(lam, prob, flats):
@@ -251,7 +267,7 @@ def _fix_gauge(lam, prob, flats):
     t_star = [_gauge_value(target, c) - _gauge_value(lam, c) for c in flats]
     t = nearest_feasible_shift(t_star, flats, lam, prob.eps)
     u = np.array(flats).T @ t
-    return [l + u[i] for i, l in enumerate(lam)]
+    return snap_to_bound(lam, u, prob.eps)
 
 
 def kkt_residual(lam, g, prob: Problem) -> float:
@@ -423,11 +439,21 @@ def solve_eigs(prob: Problem, warm=None, tol: float = 1e-15, max_iter: int = 500
     x0 = np.concatenate([lam0[l] for l in outer])
     lo = np.concatenate([np.full(prob.ranks[l], prob.eps[l]) for l in outer])
     scale = np.concatenate([0.5 * prob.E[l] for l in outer])
-    x, it, _, _ = minimize_box(evaluate, x0, lo, scale, tol, max_iter)
-    evaluate(x, False)
-    lam = [np.array(l, dtype=np.float64) for l in state["lam"]]
-    lam = [np.maximum(l, e) for l, e in zip(_fix_gauge(lam, prob, flats), prob.eps)]
-    kkt = kkt_residual(lam, grad_precise(lam, prob), prob)
+    x = x0
+    it = 0
+    for _round in range(4):
+        # minimise, then move to the start's gauge along the flat directions; the
+        # projection's own rounding can lift an eigenvalue off its bound by a
+        # few ulps of the shift, so the solve resumes until the point is stable
+        x, k_it, _, _ = minimize_box(evaluate, x, lo, scale, tol, max_iter)
+        it += k_it
+        evaluate(x, False)
+        lam = [np.array(l, dtype=np.float64) for l in state["lam"]]
+        lam = [np.maximum(l, e) for l, e in zip(_fix_gauge(lam, prob, flats), prob.eps)]
+        kkt = kkt_residual(lam, grad_precise(lam, prob), prob)
+        x = np.concatenate([lam[l] for l in outer])
+        if kkt <= max(tol, 1e-14) or not flats:
+            break
     pinned = [int(np.sum(l <= e * (1 + 1e-12))) for l, e in zip(lam, prob.eps)]
     return SolveResult(lam, it, kkt, kkt <= max(tol, 1e-14), pinned)
 

@@ -33,7 +33,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .newton import minimize_box
-from .solver import default_eps, flat_shift_space, nearest_feasible_shift
+from .solver import default_eps, flat_shift_space, nearest_feasible_shift, snap_to_bound
 
 
 @dataclass
@@ -126,7 +126,7 @@ def _fix_gauge(lam, prob, flats):
     t_star = [sum(c[l] * (target[l].sum() - lam[l].sum()) for l in range(len(lam))) for c in flats]
     t = nearest_feasible_shift(t_star, flats, lam, prob.eps)
     u = np.array(flats).T @ t
-    return [l + u[i] for i, l in enumerate(lam)]
+    return snap_to_bound(lam, u, prob.eps)
 
 
 def kkt_residual(lam, g, prob: TensorProblem) -> float:
@@ -181,8 +181,18 @@ def solve_eigs(prob: TensorProblem, warm=None, tol: float = 1e-15, max_iter: int
 
     lo = np.concatenate([np.full(prob.ranks[l], prob.eps[l]) for l in range(L)])
     scale = np.concatenate([0.5 * e for e in prob.E])
-    x, it, _, _ = minimize_box(evaluate, np.concatenate(lam0), lo, scale, tol, max_iter)
-    lam = [np.maximum(l, e) for l, e in zip(_fix_gauge([v.copy() for v in split(x)], prob, flats), prob.eps)]
-    kkt = kkt_residual(lam, grad_precise(lam, prob), prob)
+    x = np.concatenate(lam0)
+    it = 0
+    for _round in range(4):
+        # minimise, then move to the start's gauge along the flat directions; the
+        # projection's own rounding can lift an eigenvalue off its bound by a
+        # few ulps of the shift, so the solve resumes until the point is stable
+        x, k_it, _, _ = minimize_box(evaluate, x, lo, scale, tol, max_iter)
+        it += k_it
+        lam = [np.maximum(l, e) for l, e in zip(_fix_gauge([v.copy() for v in split(x)], prob, flats), prob.eps)]
+        kkt = kkt_residual(lam, grad_precise(lam, prob), prob)
+        x = np.concatenate(lam)
+        if kkt <= max(tol, 1e-14) or not flats:
+            break
     pinned = [int(np.sum(l <= e * (1 + 1e-12))) for l, e in zip(lam, prob.eps)]
     return SolveResult(lam, it, kkt, kkt <= max(tol, 1e-14), pinned)
