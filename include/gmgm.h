@@ -128,6 +128,32 @@ gmgm_status gmgm_recompose_topk(gmgm_ctx_t ctx, int64_t n, int64_t r, const floa
                                 gmgm_topk_stats* stats);
 
 /*
+ * gmgm_recompose_topk for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, checks and results, with every workspace
+ * buffer carved from a fixed device array of 128 MiB that the library holds
+ * on each device from its load until the process ends (its address is looked
+ * up when a context is created on the device).  Nothing is allocated: no
+ * hipMalloc or hipFree, no library routine that allocates, no timing events
+ * (gmgm_set_timing does not record this call).  The first sweep's workspace
+ * (V and W repacked, row norms, candidate lists) must fit: the column splits
+ * are reduced until it does, and a call whose workspace still exceeds the
+ * array is rejected with GMGM_E_SHAPE before anything is launched (BF16,
+ * r = 100: n = 100000 fits, n = 1000000 does not).  Rows the first sweep
+ * cannot certify are re-swept in FP32 when that sweep's buffers fit in what
+ * is left of the array, else scanned exactly (the result is the same).  Every
+ * call on a device shares that device's array, which keeps the last call's
+ * contents (what must start at zero is cleared by each call): calls that
+ * overlap on one device, from any context or stream, race.  Synchronises as
+ * gmgm_recompose_topk does.
+ */
+gmgm_status gmgm_recompose_topk_noalloc(gmgm_ctx_t ctx, int64_t n, int64_t r, const float* V,
+                                        const double* psi, int64_t row_begin, int64_t row_end,
+                                        int32_t k, gmgm_prec prec, int32_t cand_cap,
+                                        int64_t* row_ptr_out, int32_t* col_out, float* val_out,
+                                        gmgm_topk_stats* stats);
+
+/*
  * The rounding constant c of the certificate that makes every operand
  * precision of gmgm_recompose_topk / gmgm_recompose_threshold exact
  * (Algorithm 1, final loop, read as an exact per-row selection): with W = V

@@ -62,6 +62,8 @@ SIGNATURES = {
     "gmgm_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "gmgm_recompose_topk": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, _I64, _I32, ctypes.c_int,
                                            _I32, _P, _P, _P, ctypes.POINTER(TopkStats)]),
+    "gmgm_recompose_topk_noalloc": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, _I64, _I32, ctypes.c_int,
+                                                   _I32, _P, _P, _P, ctypes.POINTER(TopkStats)]),
     "gmgm_recompose_threshold": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _I64, _I64, ctypes.c_double, ctypes.c_int,
                                                 _I32, _P, _P, _P, _I64, ctypes.POINTER(_I64)]),
     "gmgm_significance_threshold": (ctypes.c_int, [_P, _I64, _I32, ctypes.POINTER(ctypes.c_double),
@@ -179,8 +181,11 @@ class TopkResult:
 
 
 def recompose_topk(V, psi, k: int, prec: str = "bf16", row_begin: int = 0, row_end: int | None = None,
-                   cand_cap: int = 0, stats: bool = False, check: bool = True, out=None) -> TopkResult:
-    """CSR of the per-row top-k of Psi = V diag(psi) V^T (see gmgm_recompose_topk)."""
+                   cand_cap: int = 0, stats: bool = False, check: bool = True, out=None,
+                   noalloc: bool = False, ctx=None) -> TopkResult:
+    """CSR of the per-row top-k of Psi = V diag(psi) V^T (see gmgm_recompose_topk;
+    noalloc=True calls gmgm_recompose_topk_noalloc, which allocates nothing).
+    ctx: a context handle to use instead of the device's shared one."""
     import torch
     if not (V.is_cuda and psi.is_cuda):
         raise ValueError("V and psi must be device tensors")
@@ -199,11 +204,11 @@ def recompose_topk(V, psi, k: int, prec: str = "bf16", row_begin: int = 0, row_e
         val = torch.empty(rows * k, dtype=torch.float32, device=V.device)
     else:
         rp, col, val = out
-    c = context(V.device.index)
+    c = context(V.device.index) if ctx is None else ctx
     st = TopkStats() if stats else None
-    _check(c, load().gmgm_recompose_topk(c, n, r, _ptr(V), _ptr(psi), row_begin, row_end, k, PREC[prec],
-                                          cand_cap, _ptr(rp), _ptr(col), _ptr(val),
-                                          ctypes.byref(st) if st is not None else None))
+    fn = load().gmgm_recompose_topk_noalloc if noalloc else load().gmgm_recompose_topk
+    _check(c, fn(c, n, r, _ptr(V), _ptr(psi), row_begin, row_end, k, PREC[prec], cand_cap, _ptr(rp), _ptr(col),
+                 _ptr(val), ctypes.byref(st) if st is not None else None))
     if check:
         _check(c, load().gmgm_sync(c))
     sd = None

@@ -22,6 +22,25 @@ gmgm_status hip_err(gmgm_ctx* c, hipError_t e, const char* what) {
 
 gmgm_status ws_get(gmgm_ctx* c, int slot, size_t bytes, void** out) {
   if (slot < 0 || slot >= WS_COUNT) return set_err(c, GMGM_E_ARG, "bad workspace slot");
+  if (c->arena) {
+    // fixed arena: slots are carved from it for the duration of one call and
+    // nothing is allocated; a slot asked for again with no more bytes keeps
+    // its region (so data left in it by an earlier stage stays valid)
+    if (c->arena_slots.size() < WS_COUNT) c->arena_slots.resize(WS_COUNT);
+    DevBuf& a = c->arena_slots[slot];
+    if (bytes == 0) bytes = 256;
+    if (!a.ptr || a.bytes < bytes) {
+      const size_t off = (c->arena_top + 255) & ~(size_t)255;
+      if (off > c->arena_bytes || bytes > c->arena_bytes - off)
+        return set_err(c, GMGM_E_NOMEM, "fixed workspace of %zu bytes exhausted (slot %d wants %zu more)",
+                       c->arena_bytes, slot, bytes);
+      a.ptr = (char*)c->arena + off;
+      a.bytes = bytes;
+      c->arena_top = off + bytes;
+    }
+    *out = a.ptr;
+    return GMGM_OK;
+  }
   if (c->bufs.size() < WS_COUNT) c->bufs.resize(WS_COUNT);
   DevBuf& b = c->bufs[slot];
   if (bytes == 0) bytes = 256;
@@ -44,6 +63,20 @@ gmgm_status ws_get(gmgm_ctx* c, int slot, size_t bytes, void** out) {
   }
   *out = b.ptr;
   return GMGM_OK;
+}
+
+void arena_begin(gmgm_ctx* c, void* base, size_t bytes) {
+  c->arena = base;
+  c->arena_bytes = bytes;
+  c->arena_top = 0;
+  c->arena_slots.assign(WS_COUNT, DevBuf{});
+}
+
+void arena_end(gmgm_ctx* c) {
+  c->arena = nullptr;
+  c->arena_bytes = 0;
+  c->arena_top = 0;
+  c->arena_slots.clear();
 }
 
 gmgm_status blas_handle(gmgm_ctx* c, void** out) {
@@ -80,6 +113,10 @@ extern "C" gmgm_status gmgm_create(gmgm_ctx_t* out, int device, void* stream) {
     return GMGM_E_HIP;
   }
   c->bufs.resize(WS_COUNT);
+  // the device address of the fixed workspace of the allocation-free entry
+  // point (looked up once per device, with the device current); a failure is
+  // kept and reported by that entry point
+  c->scratch_status = noalloc_scratch_address(device, &c->scratch, &c->scratch_bytes);
   *out = c;
   return GMGM_OK;
 }

@@ -32,6 +32,15 @@ struct gmgm_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;  // free events
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;   // recorded (start, stop) pairs
+  // fixed arena (set for the duration of an allocation-free call): ws_get
+  // carves slots from it instead of allocating
+  void* arena = nullptr;
+  size_t arena_bytes = 0, arena_top = 0;
+  std::vector<DevBuf> arena_slots;
+  // this device's fixed workspace of the allocation-free entry point
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  hipError_t scratch_status = hipSuccess;
 };
 
 // Record a start event on the context stream when timing is on (returns nullptr otherwise).
@@ -51,8 +60,15 @@ gmgm_status set_err(gmgm_ctx* c, gmgm_status s, const char* fmt, ...);
 gmgm_status hip_err(gmgm_ctx* c, hipError_t e, const char* what);
 // The context's rocBLAS handle (created on first use, bound to the context stream).
 gmgm_status blas_handle(gmgm_ctx* c, void** out);
-// Pointer to a workspace slot of at least `bytes` bytes (grown when needed).
+// Pointer to a workspace slot of at least `bytes` bytes (grown when needed, or
+// carved from the fixed arena while one is set).
 gmgm_status ws_get(gmgm_ctx* c, int slot, size_t bytes, void** out);
+// Carve every workspace slot from [base, base + bytes) until arena_end.
+void arena_begin(gmgm_ctx* c, void* base, size_t bytes);
+void arena_end(gmgm_ctx* c);
+// Device address and size of the fixed workspace of the allocation-free
+// recomposition entry point on `device` (the current device).
+hipError_t noalloc_scratch_address(int device, void** ptr, size_t* bytes);
 
 #define GMGM_CHECK_CTX(c)                 \
   do {                                    \

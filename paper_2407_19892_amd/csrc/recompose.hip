@@ -16,6 +16,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "recompose_sweep.h"
 
@@ -498,6 +500,11 @@ __global__ void __launch_bounds__(256) exact_scan_kernel(const float* __restrict
   }
 }
 
+__global__ void zero_words_kernel(unsigned* __restrict__ p, int words) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < words) p[t] = 0u;
+}
+
 __global__ void row_ptr_kernel(int64_t* __restrict__ rp, int64_t rows, int k) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t <= rows) rp[t] = t * k;
@@ -831,13 +838,11 @@ __global__ void __launch_bounds__(256) thr_gather_kernel(const int* __restrict__
 
 using namespace gmgm_rc;
 
-extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, const float* V,
-                                           const double* psi, int64_t row_begin, int64_t row_end,
-                                           int32_t k, gmgm_prec prec_e, int32_t cand_cap,
-                                           int64_t* row_ptr_out, int32_t* col_out, float* val_out,
-                                           gmgm_topk_stats* stats) {
-  GMGM_CHECK_CTX(c);
-  const int prec = (int)prec_e;
+// Arguments of gmgm_recompose_topk, checked before anything is launched.
+static gmgm_status topk_check(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
+                              int64_t row_begin, int64_t row_end, int32_t k, int prec, int32_t cand_cap,
+                              const int64_t* row_ptr_out, const int32_t* col_out, const float* val_out,
+                              int* C_out) {
   if (prec < 0 || prec > 2) return set_err(c, GMGM_E_ARG, "unknown precision %d", prec);
   if (n < 2 || n > 0x7fffffc0LL) return set_err(c, GMGM_E_SHAPE, "n = %lld out of range [2, 2^31 - 64]", (long long)n);
   if (r < 1 || r > 128) return set_err(c, GMGM_E_SHAPE, "r = %lld must be in [1, 128]", (long long)r);
@@ -853,6 +858,118 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
   const int C = cand_cap != 0 ? cand_cap : (prec != P_F32 || k > 12) ? 32 : 16;
   if (C != 16 && C != 32) return set_err(c, GMGM_E_ARG, "cand_cap must be 0, 16 or 32");
   if (C <= k) return set_err(c, GMGM_E_ARG, "cand_cap %d must exceed k = %d", C, k);
+  *C_out = C;
+  return GMGM_OK;
+}
+
+// Workspace of the first sweep of one gmgm_recompose_topk call (every slot it
+// asks for, each rounded up to 256 bytes as the fixed arena places them), with
+// the column splits capped at smax.
+static size_t topk_workspace_bound(int prec, int64_t n, int64_t r, int64_t row_begin, int64_t row_end, int C,
+                                   int smax) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const int kpad = kpad_for(prec, (int)r);
+  const int TI = ti_for(prec, C);
+  const int units = kpad / chunk_elems(prec) / 2;
+  const int64_t rows = row_end - row_begin;
+  const int n_vtiles = (int)ceil_div(n, 32);
+  const int n_wtiles = (int)ceil_div(row_end, 32) - (int)(row_begin / 32);
+  const int64_t w_rows = (int64_t)n_wtiles * 32;
+  const int64_t gx = ceil_div(n_wtiles, (int64_t)SW_WAVES * TI);
+  const int S = pick_splits(gx, n_vtiles, smax, 1024);
+  const int nsub = sweep_nsub(TI);
+  size_t t = 0;
+  t += up((size_t)n_vtiles * units * 64 * 16);                      // WS_VP
+  t += up((size_t)n * 4 + (size_t)w_rows * 12 + 256);                 // WS_NORMS
+  t += up(256);                                                       // WS_MISC
+  t += up((size_t)rows * 8 + 64);                                     // WS_FALLBACK
+  t += up(((size_t)n_vtiles + (size_t)w_rows) * 4 + 64);              // WS_SCALES
+  t += up((size_t)n_wtiles * units * 64 * 16);                        // WS_WP
+  t += up((size_t)rows * S * nsub * C * 8);                           // WS_CAND
+  return t;
+}
+
+static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
+                             int64_t row_begin, int64_t row_end, int32_t k, int prec, int C, int smax,
+                             int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats);
+
+extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, const float* V,
+                                           const double* psi, int64_t row_begin, int64_t row_end,
+                                           int32_t k, gmgm_prec prec_e, int32_t cand_cap,
+                                           int64_t* row_ptr_out, int32_t* col_out, float* val_out,
+                                           gmgm_topk_stats* stats) {
+  GMGM_CHECK_CTX(c);
+  int C = 0;
+  GMGM_TRY(topk_check(c, n, r, V, psi, row_begin, row_end, k, (int)prec_e, cand_cap, row_ptr_out, col_out,
+                      val_out, &C));
+  return topk_impl(c, n, r, V, psi, row_begin, row_end, k, (int)prec_e, C, 16, row_ptr_out, col_out, val_out,
+                   stats);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the same call with every workspace slot carved
+// from a fixed device array.  Each device holds its own copy of the array
+// from the library's load until the process ends; its device address is
+// looked up once per device (gmgm_create) and only that address is used.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch_address(int device, void** ptr, size_t* bytes) {
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= device) addr.resize(device + 1, nullptr);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *ptr = nullptr;
+      *bytes = 0;
+      return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    }
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  *bytes = NOALLOC_SCRATCH_BYTES;
+  return hipSuccess;
+}
+
+extern "C" gmgm_status gmgm_recompose_topk_noalloc(gmgm_ctx_t c, int64_t n, int64_t r, const float* V,
+                                                   const double* psi, int64_t row_begin, int64_t row_end,
+                                                   int32_t k, gmgm_prec prec_e, int32_t cand_cap,
+                                                   int64_t* row_ptr_out, int32_t* col_out, float* val_out,
+                                                   gmgm_topk_stats* stats) {
+  GMGM_CHECK_CTX(c);
+  int C = 0;
+  GMGM_TRY(topk_check(c, n, r, V, psi, row_begin, row_end, k, (int)prec_e, cand_cap, row_ptr_out, col_out,
+                      val_out, &C));
+  if (c->scratch_status != hipSuccess || !c->scratch)
+    return hip_err(c, c->scratch_status != hipSuccess ? c->scratch_status : hipErrorInvalidSymbol,
+                   "hipGetSymbolAddress(scratch) at context creation");
+  // fewer column splits (less parallelism for small n, shorter candidate
+  // buffers) until the first sweep's workspace fits
+  int smax = 16;
+  while (smax > 1 && topk_workspace_bound((int)prec_e, n, r, row_begin, row_end, C, smax) > c->scratch_bytes)
+    smax /= 2;
+  const size_t need = topk_workspace_bound((int)prec_e, n, r, row_begin, row_end, C, smax);
+  if (need > c->scratch_bytes)
+    return set_err(c, GMGM_E_SHAPE,
+                   "workspace of %zu bytes needed for n = %lld, r = %lld, %lld rows exceeds the fixed %zu bytes",
+                   need, (long long)n, (long long)r, (long long)(row_end - row_begin), c->scratch_bytes);
+  // no event is created while the arena is set (timing is off for this call)
+  const bool timing = c->timing;
+  c->timing = false;
+  arena_begin(c, c->scratch, c->scratch_bytes);
+  const gmgm_status s = topk_impl(c, n, r, V, psi, row_begin, row_end, k, (int)prec_e, C, smax, row_ptr_out,
+                                  col_out, val_out, stats);
+  arena_end(c);
+  c->timing = timing;
+  return s;
+}
+
+static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
+                             int64_t row_begin, int64_t row_end, int32_t k, int prec, int C, int smax,
+                             int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats) {
   GMGM_HIP(c, hipSetDevice(c->device));
   hipStream_t st = c->stream;
 
@@ -869,7 +986,7 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
   const int64_t w_lo = (int64_t)rt_begin * 32;
   const int64_t w_rows = (int64_t)n_wtiles * 32;
   const int64_t gx = ceil_div(n_wtiles, (int64_t)SW_WAVES * TI);
-  const int S = pick_splits(gx, n_vtiles, 16, 1024);
+  const int S = pick_splits(gx, n_vtiles, smax, 1024);
   const int tps = (int)ceil_div(n_vtiles, S);
 
   // ---- workspace
@@ -896,7 +1013,7 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
   int* ew = ev + n_vtiles;
 
   // ---- stage A: prep, repack, sweep in `prec`, certify
-  GMGM_HIP(c, hipMemsetAsync(misc, 0, 64, st));
+  hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, (unsigned*)misc, 16);
   const int prep_blocks = (int)std::min<int64_t>(ceil_div(n, 4), 4096);
   hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, st, V, psi, n, (int)r, w_lo,
                      std::min<int64_t>(n, w_lo + w_rows), vrowmax, wnorm, wrowmax, vmax_bits,
@@ -988,12 +1105,33 @@ extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, c
     const int tpsB = (int)ceil_div(n_vtiles, SB);
     StageBufs B;
     const int nsubB = sweep_nsub(TIB);
-    GMGM_TRY(stage_buffers(c, WS_WP2, WS_CAND2, wtB, unitsB, h1, SB, nsubB, CB, &B));
+    void* vpb = nullptr;
+    gmgm_status sB = stage_buffers(c, WS_WP2, WS_CAND2, wtB, unitsB, h1, SB, nsubB, CB, &B);
+    if (sB == GMGM_OK && !(prec == P_F32 && kpadB == kpad))
+      sB = ws_get(c, WS_VP2, (size_t)n_vtiles * unitsB * 64 * 16, &vpb);
+    if (sB != GMGM_OK) {
+      // only a fixed arena can run out here: the uncertified rows then go
+      // straight to the exact scan (same result, no re-sweep buffers)
+      if (!c->arena) return sB;
+      c->err.clear();
+      hipLaunchKernelGGL(exact_scan_kernel, dim3((unsigned)std::min(h1, 4096)), dim3(256), 0, st, V, psi, n,
+                         (int)r, k, row_begin, list1, cnt1, col_out, val_out);
+      GMGM_HIP(c, hipGetLastError());
+      if (stats) {
+        unsigned long long hc[2];
+        GMGM_HIP(c, hipMemcpyAsync(hc, counters, 16, hipMemcpyDeviceToHost, st));
+        GMGM_HIP(c, hipStreamSynchronize(st));
+        stats->cand_total = (int64_t)hc[0];
+        stats->rows_near_tie = (int64_t)hc[1];
+        stats->rows_fallback = h1;
+        stats->rows_exact = h1;
+        stats->mfma_flops = flops;
+      }
+      return GMGM_OK;
+    }
     if (prec == P_F32 && kpadB == kpad) {
       B.vp = A.vp;
     } else {
-      void* vpb;
-      GMGM_TRY(ws_get(c, WS_VP2, (size_t)n_vtiles * unitsB * 64 * 16, &vpb));
       B.vp = (const u32x4*)vpb;
       const int64_t tv = (int64_t)n_vtiles * 32 * (kpadB / 4);
       hipLaunchKernelGGL(repack_kernel<P_F32>, dim3((unsigned)ceil_div(tv, 256)), dim3(256), 0, st, V,
@@ -1116,7 +1254,7 @@ extern "C" gmgm_status gmgm_recompose_threshold(gmgm_ctx_t c, int64_t n, int64_t
   int* pool_j = (int*)pool;
   float* pool_v = (float*)((char*)pool + (size_t)pool_cap * 4);
 
-  GMGM_HIP(c, hipMemsetAsync(misc, 0, 128, st));
+  hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, (unsigned*)misc, 32);
   const int prep_blocks = (int)std::min<int64_t>(ceil_div(n, 4), 4096);
   hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, st, V, psi, n, (int)r, w_lo,
                      std::min<int64_t>(n, w_lo + w_rows), vrowmax, wnorm, wrowmax, vmax_bits,
