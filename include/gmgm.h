@@ -97,27 +97,33 @@ typedef struct {
  *   keep the k columns j != i with the largest |Psi_ij| (ties to smaller j),
  * without forming Psi.
  *
- *   n, r        V is n x r, row-major FP32 (device).  2 <= n <= 2^31 - 64, 1 <= r <= 128.
+ *   n, r        V is n x r, row-major FP32 (device).  2 <= n <= 2^31 - 64,
+ *               1 <= r <= 32768.
  *   psi         r FP64 eigenvalues (device).
  *   row_begin, row_end   0 <= row_begin < row_end <= n.
- *   k           1 <= k <= 24 and k <= n - 1.
+ *   k           1 <= k <= 64 and k <= n - 1.
  *   prec        operand precision of the first MFMA sweep (gmgm_prec).  Every
  *               precision ends the same way: candidates are rescored exactly
  *               (FP64 from the FP32 V and FP64 psi); rows whose rounding
  *               margin cannot certify the candidate set are re-swept with FP32
  *               operands, and rows that still fail are scanned exactly in FP64,
  *               so the output does not depend on `prec`.
- *   cand_cap    length of the sweep's per-lane candidate lists (16 or 32;
- *               0 picks 32 for BF16 / FP8, where a list covers a whole row,
- *               and 16 for FP32, where a list covers half a row).  Must
- *               exceed k.
+ *   cand_cap    length of the sweep's per-lane candidate lists; must exceed k.
+ *               r <= 128 and k <= 24 (W held in registers through the sweep):
+ *               16 or 32, 0 picks 32 for BF16 / FP8 (a list covers a whole
+ *               row) and 16 for FP32 (half a row).  Otherwise (the contraction
+ *               streamed in chunks of 32; FP8 requests run with BF16
+ *               operands): 32, 64 or 128, 0 picks the smallest that is at
+ *               least 2k.
  *   row_ptr_out (row_end - row_begin + 1) int64: row_ptr[t] = k * t.
  *   col_out     k * (row_end - row_begin) int32, ascending within a row.
  *   val_out     k * (row_end - row_begin) FP32: Psi_ij (signed), rounded
  *               from the FP64 rescoring.
  *   stats       host pointer or NULL; filled when non-NULL.
  * The call synchronises once after the first sweep (and once more when rows
- * need the FP32 re-sweep) to size the re-sweep of uncertified rows.
+ * need the FP32 re-sweep) to size the re-sweep of uncertified rows.  With
+ * the contraction streamed, rows the FP32 sweep cannot certify get their
+ * exact FP64 values in row panels (at most 256 MiB of workspace each).
  * Non-finite V or psi are reported as GMGM_E_DOMAIN by the next
  * synchronising call (the outputs are then undefined).
  */
@@ -163,9 +169,11 @@ gmgm_status gmgm_recompose_topk_noalloc(gmgm_ctx_t ctx, int64_t n, int64_t r, co
  * 2^-4 plus its subnormal floor; W is rounded to FP32 first), one FP32 ulp per
  * accumulation step over the padded depth, and Cauchy-Schwarz.
  *   prec        gmgm_prec value.
- *   r           the rank, 1 <= r <= 128.
+ *   r           the rank, 1 <= r <= 32768.
  *   c_out       host double: c.
- *   kpad_out    host int32 or NULL: the padded MFMA depth for r.
+ *   kpad_out    host int32 or NULL: the padded MFMA depth for r (r > 128:
+ *               the streamed sweep's, a multiple of 32, with FP8 requests
+ *               reported for their BF16 operands).
  * Host arithmetic only (no context, no device).  GMGM_E_ARG / GMGM_E_SHAPE
  * for a bad precision or rank.
  */

@@ -19,7 +19,7 @@
 #include <mutex>
 #include <vector>
 
-#include "recompose_sweep.h"
+#include "recompose_general.h"
 
 namespace gmgm_rc {
 
@@ -838,6 +838,20 @@ __global__ void __launch_bounds__(256) thr_gather_kernel(const int* __restrict__
 
 using namespace gmgm_rc;
 
+constexpr int TOPK_MAX_R = 32768;
+constexpr int TOPK_MAX_K = 64;
+
+// The register-resident sweep (W held in registers, lists of 16 or 32) serves
+// r <= 128 and k <= 24; everything else takes the K-loop sweep.
+static bool topk_fast_path(int64_t r, int k, int cand_cap) {
+  return r <= 128 && k <= 24 && (cand_cap == 0 || cand_cap == 16 || cand_cap == 32);
+}
+
+// K-loop path: the contraction padded to a multiple of 32 (one chunk), FP8
+// requests served by the BF16 sweep.
+static int kl_prec(int prec) { return prec == P_F32 ? P_F32 : P_BF16; }
+static int kl_kpad(int64_t r) { return (int)ceil_div(r, 32) * 32; }
+
 // Arguments of gmgm_recompose_topk, checked before anything is launched.
 static gmgm_status topk_check(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
                               int64_t row_begin, int64_t row_end, int32_t k, int prec, int32_t cand_cap,
@@ -845,18 +859,27 @@ static gmgm_status topk_check(gmgm_ctx* c, int64_t n, int64_t r, const float* V,
                               int* C_out) {
   if (prec < 0 || prec > 2) return set_err(c, GMGM_E_ARG, "unknown precision %d", prec);
   if (n < 2 || n > 0x7fffffc0LL) return set_err(c, GMGM_E_SHAPE, "n = %lld out of range [2, 2^31 - 64]", (long long)n);
-  if (r < 1 || r > 128) return set_err(c, GMGM_E_SHAPE, "r = %lld must be in [1, 128]", (long long)r);
+  if (r < 1 || r > TOPK_MAX_R)
+    return set_err(c, GMGM_E_SHAPE, "r = %lld must be in [1, %d]", (long long)r, TOPK_MAX_R);
   if (row_begin < 0 || row_end > n || row_begin >= row_end)
     return set_err(c, GMGM_E_SHAPE, "row range [%lld, %lld) invalid for n = %lld",
                    (long long)row_begin, (long long)row_end, (long long)n);
   if (!V || !psi || !row_ptr_out || !col_out || !val_out)
     return set_err(c, GMGM_E_ARG, "null pointer argument");
-  if (k < 1 || k > 24 || k > n - 1)
-    return set_err(c, GMGM_E_ARG, "k = %d must be in [1, min(24, n-1)]", k);
-  // Default list length: 32 per full row (BF16 / FP8 sweeps) or 16 per half row
-  // (FP32 sweep): both leave 32 candidates per row.
-  const int C = cand_cap != 0 ? cand_cap : (prec != P_F32 || k > 12) ? 32 : 16;
-  if (C != 16 && C != 32) return set_err(c, GMGM_E_ARG, "cand_cap must be 0, 16 or 32");
+  if (k < 1 || k > TOPK_MAX_K || k > n - 1)
+    return set_err(c, GMGM_E_ARG, "k = %d must be in [1, min(%d, n-1)]", k, TOPK_MAX_K);
+  if (topk_fast_path(r, k, cand_cap)) {
+    // Default list length: 32 per full row (BF16 / FP8 sweeps) or 16 per half row
+    // (FP32 sweep): both leave 32 candidates per row.
+    const int C = cand_cap != 0 ? cand_cap : (prec != P_F32 || k > 12) ? 32 : 16;
+    if (C <= k) return set_err(c, GMGM_E_ARG, "cand_cap %d must exceed k = %d", C, k);
+    *C_out = C;
+    return GMGM_OK;
+  }
+  // K-loop sweep: lists of 32, 64 or 128 per row, at least twice k by default
+  const int C = cand_cap != 0 ? cand_cap : (2 * k <= 32 ? 32 : 2 * k <= 64 ? 64 : 128);
+  if (C != 32 && C != 64 && C != 128)
+    return set_err(c, GMGM_E_ARG, "cand_cap must be 0, 16 or 32 (r <= 128, k <= 24), else 0, 32, 64 or 128");
   if (C <= k) return set_err(c, GMGM_E_ARG, "cand_cap %d must exceed k = %d", C, k);
   *C_out = C;
   return GMGM_OK;
@@ -866,8 +889,26 @@ static gmgm_status topk_check(gmgm_ctx* c, int64_t n, int64_t r, const float* V,
 // asks for, each rounded up to 256 bytes as the fixed arena places them), with
 // the column splits capped at smax.
 static size_t topk_workspace_bound(int prec, int64_t n, int64_t r, int64_t row_begin, int64_t row_end, int C,
-                                   int smax) {
+                                   int smax, int k) {
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  if (!topk_fast_path(r, k, C)) {
+    const int pk = kl_prec(prec);
+    const int units = kl_kpad(r) / chunk_elems(pk) / 2;
+    const int64_t rows = row_end - row_begin;
+    const int n_vtiles = (int)ceil_div(n, 32);
+    const int n_wtiles = (int)ceil_div(row_end, 32) - (int)(row_begin / 32);
+    const int64_t w_rows = (int64_t)n_wtiles * 32;
+    const int S = pick_splits(ceil_div(n_wtiles, (int64_t)KL_WAVES * 2), n_vtiles, smax, 1024);
+    size_t t = 0;
+    t += up((size_t)n_vtiles * units * 64 * 16);                    // WS_VP
+    t += up((size_t)n * 4 + (size_t)w_rows * 12 + 256);               // WS_NORMS
+    t += up(256);                                                     // WS_MISC
+    t += up((size_t)rows * 8 + 64);                                   // WS_FALLBACK
+    t += up((size_t)n_wtiles * units * 64 * 16);                      // WS_WP
+    t += up((size_t)rows * S * C * 8);                                // WS_CAND
+    t += up((size_t)n * 8);                                           // one exact panel row
+    return t;
+  }
   const int kpad = kpad_for(prec, (int)r);
   const int TI = ti_for(prec, C);
   const int units = kpad / chunk_elems(prec) / 2;
@@ -892,6 +933,9 @@ static size_t topk_workspace_bound(int prec, int64_t n, int64_t r, int64_t row_b
 static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
                              int64_t row_begin, int64_t row_end, int32_t k, int prec, int C, int smax,
                              int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats);
+static gmgm_status topk_general(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
+                                int64_t row_begin, int64_t row_end, int32_t k, int prec, int C, int smax,
+                                int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats);
 
 extern "C" gmgm_status gmgm_recompose_topk(gmgm_ctx_t c, int64_t n, int64_t r, const float* V,
                                            const double* psi, int64_t row_begin, int64_t row_end,
@@ -949,9 +993,9 @@ extern "C" gmgm_status gmgm_recompose_topk_noalloc(gmgm_ctx_t c, int64_t n, int6
   // fewer column splits (less parallelism for small n, shorter candidate
   // buffers) until the first sweep's workspace fits
   int smax = 16;
-  while (smax > 1 && topk_workspace_bound((int)prec_e, n, r, row_begin, row_end, C, smax) > c->scratch_bytes)
+  while (smax > 1 && topk_workspace_bound((int)prec_e, n, r, row_begin, row_end, C, smax, k) > c->scratch_bytes)
     smax /= 2;
-  const size_t need = topk_workspace_bound((int)prec_e, n, r, row_begin, row_end, C, smax);
+  const size_t need = topk_workspace_bound((int)prec_e, n, r, row_begin, row_end, C, smax, k);
   if (need > c->scratch_bytes)
     return set_err(c, GMGM_E_SHAPE,
                    "workspace of %zu bytes needed for n = %lld, r = %lld, %lld rows exceeds the fixed %zu bytes",
@@ -971,6 +1015,9 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
                              int64_t row_begin, int64_t row_end, int32_t k, int prec, int C, int smax,
                              int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats) {
   GMGM_HIP(c, hipSetDevice(c->device));
+  if (!topk_fast_path(r, k, C))
+    return topk_general(c, n, r, V, psi, row_begin, row_end, k, prec, C, smax, row_ptr_out, col_out, val_out,
+                        stats);
   hipStream_t st = c->stream;
 
   const int kpad = kpad_for(prec, (int)r);
@@ -1186,6 +1233,192 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
     stats->rows_near_tie = (int64_t)hc[1];
     stats->rows_fallback = h1;
     stats->rows_exact = h2;
+    stats->mfma_flops = flops;
+  }
+  return GMGM_OK;
+}
+
+// The K-loop path: prep, repack (contraction padded to a multiple of 32), the
+// K-loop sweep, exact rescoring and certificate; uncertified rows of a BF16
+// sweep are re-swept in FP32; rows that still fail get exact FP64 panels.
+static gmgm_status topk_general(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
+                                int64_t row_begin, int64_t row_end, int32_t k, int prec_in, int C, int smax,
+                                int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats) {
+  hipStream_t st = c->stream;
+  const int prec = kl_prec(prec_in);
+  const int kpad = kl_kpad(r);
+  const int units = kpad / chunk_elems(prec) / 2;
+  const int64_t rows = row_end - row_begin;
+  const int n_vtiles = (int)ceil_div(n, 32);
+  const int rt_begin = (int)(row_begin / 32);
+  const int n_wtiles = (int)ceil_div(row_end, 32) - rt_begin;
+  const int64_t w_lo = (int64_t)rt_begin * 32;
+  const int64_t w_rows = (int64_t)n_wtiles * 32;
+  const int64_t gx = ceil_div(n_wtiles, (int64_t)KL_WAVES * 2);
+  const int S = pick_splits(gx, n_vtiles, smax, 1024);
+  const int tps = (int)ceil_div(n_vtiles, S);
+
+  void *vp, *norms, *misc, *lists, *wp, *cand;
+  GMGM_TRY(ws_get(c, WS_VP, (size_t)n_vtiles * units * 64 * 16, &vp));
+  GMGM_TRY(ws_get(c, WS_NORMS, (size_t)n * 4 + (size_t)w_rows * 12 + 256, &norms));
+  GMGM_TRY(ws_get(c, WS_MISC, 256, &misc));
+  GMGM_TRY(ws_get(c, WS_FALLBACK, (size_t)rows * 8 + 64, &lists));
+  GMGM_TRY(ws_get(c, WS_WP, (size_t)n_wtiles * units * 64 * 16, &wp));
+  const size_t ncand = (size_t)rows * S * C;
+  GMGM_TRY(ws_get(c, WS_CAND, ncand * 8, &cand));
+  float* vrowmax = (float*)norms;
+  double* wnorm = (double*)((char*)norms + (((size_t)n * 4 + 15) & ~(size_t)15));
+  float* wrowmax = (float*)(wnorm + w_rows);
+  unsigned* vmax_bits = (unsigned*)misc;
+  int* cnt1 = (int*)((char*)misc + 16);
+  int* cnt2 = (int*)((char*)misc + 20);
+  unsigned long long* counters = (unsigned long long*)((char*)misc + 32);
+  int* list1 = (int*)lists;
+  int* list2 = list1 + rows;
+
+  hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, (unsigned*)misc, 16);
+  const int prep_blocks = (int)std::min<int64_t>(ceil_div(n, 4), 4096);
+  hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, st, V, psi, n, (int)r, w_lo,
+                     std::min<int64_t>(n, w_lo + w_rows), vrowmax, wnorm, wrowmax, vmax_bits, c->dev_status);
+  const int nch = kpad / chunk_elems(prec);
+  launch_repack(prec, [&](auto kern) {
+    const int64_t tv = (int64_t)n_vtiles * 32 * nch, tw = w_rows * nch;
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(tv, 256)), dim3(256), 0, st, V, psi, (int64_t)0, n,
+                       (int64_t)n_vtiles * 32, (int)r, kpad, false, (const int*)nullptr, true, (const int*)nullptr,
+                       (const int*)nullptr, (u32x4*)vp);
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(tw, 256)), dim3(256), 0, st, V, psi, w_lo, n, w_rows,
+                       (int)r, kpad, true, (const int*)nullptr, false, (const int*)nullptr, (const int*)nullptr,
+                       (u32x4*)wp);
+  });
+  KloopArgs ka{};
+  ka.Vp = (const u32x4*)vp;
+  ka.Wp = (const u32x4*)wp;
+  ka.cval = (float*)cand;
+  ka.cidx = (int*)((char*)cand + ncand * 4);
+  ka.n = n;
+  ka.n_vtiles = n_vtiles;
+  ka.n_wtiles = n_wtiles;
+  ka.units = units;
+  ka.row0 = w_lo;
+  ka.row_begin = row_begin;
+  ka.row_end = row_end;
+  ka.S = S;
+  ka.tiles_per_split = tps;
+  ka.wnorm = wnorm;
+  ka.vmax_bits = vmax_bits;
+  ka.w_lo = w_lo;
+  ka.cprec = cprec_for(prec, kpad);
+  ka.k = k;
+  hipEvent_t t0 = timing_start(c);
+  launch_sweep_kloop(prec, C, gx, S, st, ka);
+  timing_stop(c, t0);
+  FinalGenArgs fa{};
+  fa.cval = ka.cval;
+  fa.cidx = ka.cidx;
+  fa.V = V;
+  fa.psi = psi;
+  fa.wnorm = wnorm;
+  fa.vmax_bits = vmax_bits;
+  fa.n = n;
+  fa.r = (int)r;
+  fa.k = k;
+  fa.C = C;
+  fa.S = S;
+  fa.row_begin = row_begin;
+  fa.rows = rows;
+  fa.w_lo = w_lo;
+  fa.cprec = ka.cprec;
+  fa.col_out = col_out;
+  fa.val_out = val_out;
+  fa.fail_list = list1;
+  fa.fail_count = cnt1;
+  fa.counters = stats ? counters : nullptr;
+  launch_finalize_gen(rows, st, fa);
+  hipLaunchKernelGGL(row_ptr_kernel, dim3((unsigned)ceil_div(rows + 1, 256)), dim3(256), 0, st, row_ptr_out, rows,
+                     k);
+  GMGM_HIP(c, hipGetLastError());
+  double flops = 2.0 * (double)w_rows * 32.0 * n_vtiles * kpad;
+
+  int h1 = 0, h2 = 0;
+  GMGM_HIP(c, hipMemcpyAsync(&h1, cnt1, 4, hipMemcpyDeviceToHost, st));
+  GMGM_HIP(c, hipStreamSynchronize(st));
+  const int* exact_list = list1;
+  int h_exact = h1;
+  if (h1 > 0 && prec != P_F32 && !c->arena) {
+    // FP32 re-sweep of the rows the BF16 sweep could not certify (with a fixed
+    // arena the rows go straight to the exact panels, which need less room)
+    const int unitsB = kpad / chunk_elems(P_F32) / 2;
+    const int64_t wtB = ceil_div(h1, 32);
+    const int64_t gxB = ceil_div(wtB, (int64_t)KL_WAVES * 2);
+    const int SB = pick_splits(gxB, n_vtiles, 64, 1024);
+    const size_t ncandB = (size_t)h1 * SB * C;
+    void *vpb, *wpb, *candb;
+    GMGM_TRY(ws_get(c, WS_VP2, (size_t)n_vtiles * unitsB * 64 * 16, &vpb));
+    GMGM_TRY(ws_get(c, WS_WP2, (size_t)wtB * unitsB * 64 * 16, &wpb));
+    GMGM_TRY(ws_get(c, WS_CAND2, ncandB * 8, &candb));
+    {
+      const int64_t tv = (int64_t)n_vtiles * 32 * (kpad / 4), twB = wtB * 32 * (kpad / 4);
+      hipLaunchKernelGGL(repack_kernel<P_F32>, dim3((unsigned)ceil_div(tv, 256)), dim3(256), 0, st, V, psi,
+                         (int64_t)0, n, (int64_t)n_vtiles * 32, (int)r, kpad, false, (const int*)nullptr, true,
+                         (const int*)nullptr, (const int*)nullptr, (u32x4*)vpb);
+      hipLaunchKernelGGL(repack_kernel<P_F32>, dim3((unsigned)ceil_div(twB, 256)), dim3(256), 0, st, V, psi,
+                         (int64_t)0, n, wtB * 32, (int)r, kpad, true, (const int*)nullptr, false,
+                         (const int*)list1, (const int*)cnt1, (u32x4*)wpb);
+      KloopArgs kb = ka;
+      kb.Vp = (const u32x4*)vpb;
+      kb.Wp = (const u32x4*)wpb;
+      kb.cval = (float*)candb;
+      kb.cidx = (int*)((char*)candb + ncandB * 4);
+      kb.row_list = list1;
+      kb.row_count = cnt1;
+      kb.n_wtiles = (int)wtB;
+      kb.units = unitsB;
+      kb.S = SB;
+      kb.tiles_per_split = (int)ceil_div(n_vtiles, SB);
+      kb.cprec = cprec_for(P_F32, kpad);
+      launch_sweep_kloop(P_F32, C, gxB, SB, st, kb);
+      FinalGenArgs fb = fa;
+      fb.cval = kb.cval;
+      fb.cidx = kb.cidx;
+      fb.S = SB;
+      fb.row_list = list1;
+      fb.row_count = cnt1;
+      fb.cprec = kb.cprec;
+      fb.fail_list = list2;
+      fb.fail_count = cnt2;
+      fb.counters = stats ? counters + 2 : nullptr;
+      launch_finalize_gen(h1, st, fb);
+      GMGM_HIP(c, hipGetLastError());
+      flops += 2.0 * (double)wtB * 32.0 * n_vtiles * 32.0 * kpad;
+      GMGM_HIP(c, hipMemcpyAsync(&h2, cnt2, 4, hipMemcpyDeviceToHost, st));
+      GMGM_HIP(c, hipStreamSynchronize(st));
+      exact_list = list2;
+      h_exact = h2;
+    }
+  }
+  if (h_exact > 0) {
+    // exact FP64 values of whole rows, a panel of rows at a time
+    const size_t row_bytes = (size_t)n * 8;
+    size_t room = (size_t)256 << 20;
+    if (c->arena) room = c->arena_bytes - std::min(c->arena_bytes, ((c->arena_top + 255) & ~(size_t)255));
+    const int64_t prow = std::max<int64_t>(1, std::min<int64_t>(h_exact, (int64_t)(room / row_bytes)));
+    void* panel;
+    GMGM_TRY(ws_get(c, WS_THR0, (size_t)prow * row_bytes, &panel));
+    for (int64_t q0 = 0; q0 < h_exact; q0 += prow) {
+      const int pr = (int)std::min<int64_t>(prow, h_exact - q0);
+      launch_exact_panel(V, psi, n, (int)r, exact_list, (int)q0, pr, (double*)panel, st);
+      launch_panel_topk((const double*)panel, n, exact_list, (int)q0, pr, k, row_begin, col_out, val_out, st);
+    }
+    GMGM_HIP(c, hipGetLastError());
+  }
+  if (stats) {
+    unsigned long long hc[2];
+    GMGM_HIP(c, hipMemcpyAsync(hc, counters, 16, hipMemcpyDeviceToHost, st));
+    GMGM_HIP(c, hipStreamSynchronize(st));
+    stats->cand_total = (int64_t)hc[0];
+    stats->rows_near_tie = (int64_t)hc[1];
+    stats->rows_fallback = h1;
+    stats->rows_exact = h_exact;
     stats->mfma_flops = flops;
   }
   return GMGM_OK;
@@ -1465,8 +1698,10 @@ extern "C" gmgm_status gmgm_significance_threshold(gmgm_ctx_t c, int64_t d_l, in
 
 extern "C" gmgm_status gmgm_rounding_bound(int32_t prec, int64_t r, double* c_out, int32_t* kpad_out) {
   if (prec < 0 || prec > 2 || !c_out) return GMGM_E_ARG;
-  if (r < 1 || r > 128) return GMGM_E_SHAPE;
-  const int kpad = kpad_for(prec, (int)r);
+  if (r < 1 || r > TOPK_MAX_R) return GMGM_E_SHAPE;
+  // r > 128 takes the K-loop sweep (FP8 requests run in BF16 there)
+  if (r > 128) prec = kl_prec(prec);
+  const int kpad = r <= 128 ? kpad_for(prec, (int)r) : kl_kpad(r);
   *c_out = cprec_for(prec, kpad);
   if (kpad_out) *kpad_out = kpad;
   return GMGM_OK;

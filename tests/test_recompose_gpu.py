@@ -128,9 +128,9 @@ def test_argument_errors(lib):
         with pytest.raises(lib.GmgmError) as ei:
             lib.recompose_topk(V, psi, k, **kw)
         assert ei.value.status == status
-    W = torch.ones(64, 200, dtype=torch.float32, device="cuda")
+    W = torch.ones(4, 40000, dtype=torch.float32, device="cuda")
     with pytest.raises(lib.GmgmError):
-        lib.recompose_topk(W, torch.ones(200, dtype=torch.float64, device="cuda"), 3)
+        lib.recompose_topk(W, torch.ones(40000, dtype=torch.float64, device="cuda"), 3)
 
 
 def test_repeat_calls_are_deterministic(lib):

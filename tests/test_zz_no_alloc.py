@@ -87,6 +87,12 @@ def test_noalloc_matches_allocating_call_twice_in_a_row(lib):
         p3 = 1.0 / synth.spectrum_proxy(64, 3001, 6, seed=42)[:33]
         a3, b3 = _both(lib, ctx, V3, p3, 7, "fp32", row_begin=17, row_end=2500)
         _same(a3, b3)
+        # the streamed-contraction path (r = 300) with rows that need the exact panels
+        A3 = _adversarial.aligned_rounding_rows("bf16", k=10, r=300)
+        a4, b4 = _both(lib, ctx, A3["V"], A3["psi"], 10, "bf16")
+        _same(a4, b4)
+        assert a4.stats["rows_exact"] >= 1, a4.stats
+        _oracle_rows(A3["V"], A3["psi"], 10, np.arange(A3["V"].shape[0]), a4.col.cpu().numpy(), "r=300")
     finally:
         lib.load().gmgm_destroy(ctx)
 
