@@ -36,11 +36,37 @@ if ROOT not in sys.path:
 
 METRIC = "top-k precision rows/s at 1M cells, BF16-MFMA vs FP32, recall ≥0.999"
 PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
-# HBM traffic of the BF16 sweep kernel at this workload, from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE runs scaled by the counters' readings on a 1 GiB copy (factors 2.0 and
-# 1.0); see profiles/recompose_bf16_1M_r100_k10_hbm_counters.md.  Keyed by the
-# kernel instantiation; set to None whenever that kernel changes.
-SWEEP_TRAFFIC_BYTES = {("bf16", 1_000_000, 100, 10): (9116101.9 * 2.0 + 250000.0) * 1024}
+# HBM traffic of the BF16 sweep kernel at this workload comes from the committed
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summary, which records the SHA-256 of the
+# sweep's sources it was taken on; when the sources differ the figure no longer
+# describes the kernel and traffic is reported as null.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "recompose_bf16_1M_r100_k10_hbm_counters.md")
+SWEEP_SOURCES = ["recompose_sweep.h", "sweep_bf16_c32.hip", "mfma_util.h", "recompose.hip"]
+
+
+def sweep_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2407_19892_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_sweep_traffic(prec, n, r, k):
+    """(bytes per launch, note) of the BF16 sweep from the counter summary."""
+    if (prec, n, r, k) != ("bf16", 1_000_000, 100, 10) or not os.path.exists(TRAFFIC_PROFILE):
+        return None, "no counter profile for this configuration"
+    vals = {}
+    with open(TRAFFIC_PROFILE) as f:
+        for line in f:
+            if line.startswith("sweep_traffic_bytes_per_launch:"):
+                vals["bytes"] = float(line.split(":", 1)[1])
+            elif line.startswith("sweep_sources_sha256:"):
+                vals["sha"] = line.split(":", 1)[1].strip()
+    if "bytes" not in vals or vals.get("sha") != sweep_sources_sha256():
+        return None, "the sweep's sources changed since the counters were taken"
+    return vals["bytes"], os.path.relpath(TRAFFIC_PROFILE, ROOT)
 
 
 def log(*a):
@@ -48,7 +74,11 @@ def log(*a):
 
 
 def workload(n, r, seed=3000):
-    """Cell factor of the 1M x 20k, 5%-dense, 40-cluster workload and its psi."""
+    """Stand-ins for the cell factor of the 1M x 20k, 5%-dense, 40-cluster
+    workload (synth.cell_factor_proxy: orthonormal columns spanning 40 Zipf
+    cluster centroids, the rank-8 factor and per-cell noise) and its psi (1/E of
+    a Marchenko-Pastur + spike spectrum of a 20k-gene Gram).  The chain's own
+    factor and solved psi are timed in stages["chain_recompose"]."""
     import numpy as np
 
     import synth
@@ -58,31 +88,38 @@ def workload(n, r, seed=3000):
     return V, psi
 
 
-def cpu_baseline(V, psi, k, budget_s=15.0):
-    """The CPU oracle (unchanged) on a bounded sample of rows of the same workload."""
+def cpu_baseline(V, psi, k, n_clusters=40, seed=3000, per_cluster=4, edge=32):
+    """The CPU oracle (unchanged) on a stratified sample of rows of the same
+    workload: the first and last `edge` rows and `per_cluster` random rows of
+    every cluster (about 20 s of CPU work at this size)."""
     import numpy as np
 
     import oracle
+    import synth
     try:
         from threadpoolctl import threadpool_info
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
     except Exception:
         cores = os.cpu_count()
     n = V.shape[0]
-    rows_done, t_used, m = 0, 0.0, 4
+    labels = synth.cluster_labels(n, n_clusters, True, seed)
     rng = np.random.default_rng(7)
-    while t_used < budget_s and rows_done < 4096:
-        rows = np.sort(rng.choice(n, m, replace=False))
-        t0 = time.perf_counter()
-        P = oracle.psi_rows(V, psi, rows)
-        oracle.topk_csr(P, rows, k)
-        dt = time.perf_counter() - t0
-        rows_done += m
-        t_used += dt
-        m = max(1, min(256, int(m * max(1.0, (budget_s - t_used) / max(dt, 1e-3)) * 0.5)))
-    return {"value": rows_done / t_used, "unit": "rows/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{rows_done} random rows of the n={n}, r={V.shape[1]}, k={k} workload "
-                      f"(FP64 row recomposition + exact top-k), {t_used:.1f} s"}
+    picks = [np.arange(edge), np.arange(n - edge, n)]
+    for c in range(n_clusters):
+        members = np.flatnonzero(labels == c)
+        picks.append(rng.choice(members, min(per_cluster, members.size), replace=False))
+    rows = np.unique(np.concatenate(picks))
+    t0 = time.perf_counter()
+    for lo in range(0, rows.size, 16):
+        blk = rows[lo:lo + 16]
+        P = oracle.psi_rows(V, psi, blk)
+        oracle.topk_csr(P, blk, k)
+    dt = time.perf_counter() - t0
+    return {"value": rows.size / dt, "unit": "rows/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{rows.size} rows of the n={n}, r={V.shape[1]}, k={k} workload: rows 0-{edge - 1}, "
+                      f"the last {edge}, {per_cluster} random rows of each of the {n_clusters} clusters "
+                      f"(FP64 row recomposition + exact top-k), {dt:.1f} s; all {n} rows would take "
+                      f"{n / (rows.size / dt) / 3600:.1f} h (extrapolated)"}
 
 
 def stages(g, n, p, r, workers, multimodal=True):
@@ -122,11 +159,19 @@ def stages(g, n, p, r, workers, multimodal=True):
     wall, kms, cnt, _ = timed(lambda: g.gram(rpd, cd, vd, n, p, out=G), 1)
     pp = (p + 255) // 256 * 256
     dense = float(n) * pp * pp                            # 2 n pp^2 / 2: upper tiles incl. diagonal tiles
+    row_nnz = np.diff(rpd.cpu().numpy()).astype(np.float64)
+    algo = float(np.sum(row_nnz * (row_nnz + 1.0)))      # 2 sum_c nnz_c (nnz_c + 1) / 2: the method's products
     out["gram"] = {"ms": wall * 1e3, "tile_kernel_ms": kms, "launches": cnt, "bound": "mfma",
-                   "unit": "TFLOP/s", "achieved": dense / (kms * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp32"],
-                   "frac": dense / (kms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
-                   "flops_per_launch_set": dense, "flops_kind": "dense FP32 MFMA, n * p_pad^2 (symmetric half)"}
-    log(f"stages: gram {wall * 1e3:.1f} ms ({out['gram']['achieved']:.1f} TF/s)")
+                   "unit": "TFLOP/s", "achieved": algo / (kms * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp32"],
+                   "frac": algo / (kms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+                   "algorithmic_flops": algo,
+                   "flops_kind": "2 sum_c nnz_c (nnz_c + 1) / 2: products of each cell's nonzeros (upper half)",
+                   "executed_dense_flops": dense,
+                   "executed_tflops": dense / (kms * 1e-3) / 1e12,
+                   "executed_frac": dense / (kms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+                   "executed_kind": "dense-panel FP32 MFMA, n * p_pad^2 (upper tiles)"}
+    log(f"stages: gram {wall * 1e3:.1f} ms ({out['gram']['achieved']:.2f} TF/s algorithmic, "
+        f"{out['gram']['executed_tflops']:.1f} TF/s executed)")
     wall, kms, cnt, res = timed(lambda: g.eigh_small(G), 1)
     w, Vt, rank = res
     out["eigh"] = {"ms": wall * 1e3, "solver_ms": kms, "p": p, "rank": rank,
@@ -148,6 +193,7 @@ def stages(g, n, p, r, workers, multimodal=True):
     out["solve"] = {"ms": wall * 1e3, "r_c": r, "r_g": rank, **{k: sol.info[k] for k in
                                                             ("iterations", "kkt", "n_pinned")}}
     log(f"stages: solve {wall * 1e3:.1f} ms, {sol.info['iterations']} iterations")
+    out["chain_recompose"] = chain_recompose(g, U, sol.lam[0].contiguous(), 10)
     # the Nonparanormal Skeptic of the same matrix kept sparse (S + 1 z^T), and
     # the Gram of the transform through the rank-two correction
     del Vt, U
@@ -170,6 +216,7 @@ def stages(g, n, p, r, workers, multimodal=True):
     del rpd, cd, vd
     torch.cuda.empty_cache()
     out["tensor_solve"] = tensor_solve(g)
+    out["gene_axis_recompose"] = gene_axis_recompose(g)
     return out
 
 
@@ -180,24 +227,116 @@ def tensor_solve(g):
     import numpy as np
     import torch
 
-    from tests._tensor_inputs import coil_like_spectra
+    import synth
     t0 = time.perf_counter()
-    E, mods = coil_like_spectra(seed=1)
-    out = {"input": "Gram spectra of 20 synthetic rotating-object videos, 72 x 128 x 128, seed 1",
+    E, mods = library_spectra(g, synth.rotating_objects(20, 72, 128, 128, seed=1))
+    out = {"input": "Gram spectra (library Gram + FP64 eigendecomposition of each unfolding) of 20 "
+                    "synthetic rotating-object videos, 72 x 128 x 128, seed 1",
            "axes": len(E), "modalities": len(mods)}
     log(f"stages: tensor spectra in {time.perf_counter() - t0:.1f} s")
     for label, r in (("top10", 10), ("all", None)):
-        Ed = [torch.from_numpy(np.ascontiguousarray(e[:r] if r else e)).cuda() for e in E]
-        g.solve_eigs_tensor(Ed, mods)                     # warm-up (workspace, library handles)
+        Ed = [e[:r].contiguous() if r else e for e in E]
+        g.solve_eigs_tensor(Ed, mods, max_iter=1000, raise_on_noconv=False)   # warm-up (workspace, handles)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        sol = g.solve_eigs_tensor(Ed, mods)
+        sol = g.solve_eigs_tensor(Ed, mods, max_iter=1000, raise_on_noconv=False)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
         out[label] = {"ms": wall * 1e3, "unknowns": int(sum(e.numel() for e in Ed)),
-                      **{k: sol.info[k] for k in ("iterations", "kkt", "n_flat")}}
+                      **{k: sol.info[k] for k in ("iterations", "kkt", "n_flat", "converged")}}
         log(f"stages: tensor solve ({label}) {wall * 1e3:.1f} ms, {sol.info['iterations']} iterations")
     return out
+
+
+def library_spectra(g, tensors):
+    """Per-axis Gram spectra of order-3 tensors (frames x h x w) sharing the frame
+    axis, computed with the library: each unfolding as a dense CSR, gmgm_gram,
+    gmgm_eigh_small, the numerically nonzero eigenvalues."""
+    import numpy as np
+    import torch
+
+    def spectrum(A):                                     # Gram of A's columns: A^T A
+        m, p = A.shape
+        rp = torch.arange(m + 1, dtype=torch.int64, device="cuda") * p
+        col = torch.arange(p, dtype=torch.int32, device="cuda").repeat(m)
+        val = torch.from_numpy(np.ascontiguousarray(A, dtype=np.float32)).cuda().view(-1)
+        w, _, rank = g.eigh_small(g.gram(rp, col, val, m, p))
+        return w[:rank].contiguous()
+
+    frames = tensors[0].shape[0]
+    E = [spectrum(np.concatenate([X.reshape(frames, -1).T for X in tensors], axis=0))]
+    mods = []
+    for i, X in enumerate(tensors):
+        E.append(spectrum(np.moveaxis(X, 1, 0).reshape(X.shape[1], -1).T))
+        E.append(spectrum(np.moveaxis(X, 2, 0).reshape(X.shape[2], -1).T))
+        mods.append((0, 1 + 2 * i, 2 + 2 * i))
+    return E, mods
+
+
+def chain_recompose(g, U, psi, k, prec="bf16", steps=3):
+    """The metric's recomposition on the chain's own output: the cell factor
+    from gmgm_sketch of the CSR above and psi from gmgm_solve_eigs of its
+    spectra."""
+    import torch
+    n, r = U.shape
+    out = (torch.empty(n + 1, dtype=torch.int64, device="cuda"), torch.empty(n * k, dtype=torch.int32, device="cuda"),
+           torch.empty(n * k, dtype=torch.float32, device="cuda"))
+    g.recompose_topk(U, psi, k, prec=prec, out=out)
+    g.sync()
+    g.kernel_times()
+    g.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.recompose_topk(U, psi, k, prec=prec, out=out, check=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    g.set_timing(False)
+    sweep_ms, cnt = g.kernel_times()
+    sweep_ms /= max(cnt, 1)
+    st = g.recompose_topk(U, psi, k, prec=prec, out=out, stats=True).stats
+    flops = 2.0 * r * n * n
+    log(f"stages: chain recompose {dt * 1e3:.1f} ms/step, sweep {sweep_ms:.1f} ms, stats {st}")
+    return {"input": "cell factor of the CSR stand-in (gmgm_sketch, r = %d) and its solved psi" % r,
+            "rows_per_s": n / dt, "ms_per_step": dt * 1e3, "sweep_ms": sweep_ms,
+            "sweep_frac_of_peak": flops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], "stats": st}
+
+
+def gene_axis_recompose(g, n=20_000, k=10, seed=3000):
+    """Recomposition + top-k of a full-rank gene axis at the 1M x 20k workload's
+    size (n = r = 20k, the contraction streamed): a Gaussian factor and psi = 1/E
+    of a Marchenko-Pastur + spike spectrum (at this workload the solved gene
+    eigenvalues all sit at their bound, which makes Psi_g a multiple of I)."""
+    import numpy as np
+    import torch
+
+    import synth
+    rng = np.random.default_rng(seed)
+    V = torch.from_numpy((rng.standard_normal((n, n), dtype=np.float32) / np.float32(np.sqrt(n)))).cuda()
+    psi = torch.from_numpy(1.0 / synth.spectrum_proxy(n, 1_000_000, 40, seed=seed)).cuda()
+    res = {"input": f"{n} x {n} Gaussian factor, r = {n}, k = {k}"}
+    for prec in ("fp32", "bf16"):
+        g.recompose_topk(V, psi, k, prec=prec)
+        g.sync()
+        g.kernel_times()
+        g.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = g.recompose_topk(V, psi, k, prec=prec, stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.set_timing(False)
+        sweep_ms, cnt = g.kernel_times()
+        flops = 2.0 * n * n * ((n + 31) // 32 * 32)
+        res[prec] = {"ms": dt * 1e3, "sweep_ms": sweep_ms, "sweep_tflops": flops / (sweep_ms * 1e-3) / 1e12,
+                     "sweep_frac_of_peak": flops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
+                     "stats": o.stats}
+        log(f"stages: gene axis {prec}: {dt * 1e3:.1f} ms, sweep {sweep_ms:.1f} ms "
+            f"({res[prec]['sweep_tflops']:.1f} TF/s), stats {o.stats}")
+        del o
+    del V, psi
+    torch.cuda.empty_cache()
+    return res
 
 
 def shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, workers, p_pk=50_000, k_over=10, q=2):
@@ -332,10 +471,14 @@ def main():
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timings")
     ap.add_argument("--no-multimodal", action="store_true", help="skip the shared-cell-axis stage")
     ap.add_argument("--profile-run", action="store_true", help="one step + a 1 GiB copy, no JSON")
+    ap.add_argument("--sources-sha", action="store_true", help="print the SHA-256 of the sweep's sources")
     ap.add_argument("--tensor-solve-only", action="store_true",
                     help="only the tensor-variate eigenvalue solve at the COIL-20 shape (its own JSON line)")
     args = ap.parse_args()
 
+    if args.sources_sha:
+        print(sweep_sources_sha256())
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
@@ -392,18 +535,20 @@ def main():
     log(f"{args.prec}: {step_s * 1e3:.2f} ms/step, sweep {sweep_ms:.2f} ms, stats {st_main}")
 
     flops = 2.0 * r * n * n
+    traffic, traffic_note = profiled_sweep_traffic(args.prec, n, r, k)
     result = {
         "metric": METRIC, "value": n / step_s, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": "cell-axis recomposition + top-k of the 1M cells x 20k genes "
-                               "(5% CSR, 40 Zipf clusters) workload: n=1,000,000, r=100, k=10",
+        "config": {"workload": "cell-axis recomposition + top-k at the 1M cells x 20k genes workload's "
+                               "shape (n=1,000,000, r=100, k=10) on a stand-in cell factor (orthonormal, "
+                               "40 Zipf clusters) and psi = 1/E of a Marchenko-Pastur + spike spectrum",
                    "n": n, "r": r, "k": k, "prec": args.prec, "global_batch": n, "seq_len": None,
                    "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "mfma", "kernel": "sweep_kernel",
                      "achieved": flops / (sweep_ms * 1e-3) / 1e12, "peak": PEAK_TFLOPS[args.prec],
                      "unit": "TFLOP/s", "frac": flops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
-                     "traffic": SWEEP_TRAFFIC_BYTES.get((args.prec, n, r, k)), "traffic_unit": "bytes",
+                     "traffic": traffic, "traffic_unit": "bytes", "traffic_source": traffic_note,
                      "sweep_ms": sweep_ms,
                      "algorithmic_flops_per_launch": flops, "executed_mfma_flops": st_main["mfma_flops"]},
         "stats": st_main,

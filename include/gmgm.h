@@ -80,10 +80,10 @@ gmgm_status gmgm_kernel_times(gmgm_ctx_t ctx, double* total_ms, int64_t* count);
 /* Counters of one gmgm_recompose_topk call (filled only when requested). */
 typedef struct {
   int64_t cand_total;       /* candidates (approximate top-C entries) kept by the sweep */
-  int64_t rows_fallback;    /* rows the first sweep could not certify (re-swept in FP32) */
+  int64_t rows_fallback;    /* rows the first sweep could not certify (re-swept) */
   int64_t rows_near_tie;    /* certified rows whose k-th and (k+1)-th exact |Psi| differ
                                by < 1e-6 relative */
-  int64_t rows_exact;       /* rows the FP32 re-sweep could not certify either (exact
+  int64_t rows_exact;       /* rows the re-sweep could not certify either (exact
                                FP64 scan of the whole row) */
   double mfma_flops;        /* MFMA flops executed by the sweeps (padded K) */
 } gmgm_topk_stats;
@@ -105,9 +105,12 @@ typedef struct {
  *   prec        operand precision of the first MFMA sweep (gmgm_prec).  Every
  *               precision ends the same way: candidates are rescored exactly
  *               (FP64 from the FP32 V and FP64 psi); rows whose rounding
- *               margin cannot certify the candidate set are re-swept with FP32
- *               operands, and rows that still fail are scanned exactly in FP64,
- *               so the output does not depend on `prec`.
+ *               margin cannot certify the candidate set are re-swept (r <= 128
+ *               and k <= 24: FP32 operands after an FP32 sweep, else each
+ *               FP32 operand split into two BF16 parts hi + lo with
+ *               hi*hi + hi*lo + lo*hi formed on the matrix cores; otherwise
+ *               FP32 operands), and rows that still fail are scanned exactly
+ *               in FP64, so the output does not depend on `prec`.
  *   cand_cap    length of the sweep's per-lane candidate lists; must exceed k.
  *               r <= 128 and k <= 24 (W held in registers through the sweep):
  *               16 or 32, 0 picks 32 for BF16 / FP8 (a list covers a whole
@@ -121,7 +124,7 @@ typedef struct {
  *               from the FP64 rescoring.
  *   stats       host pointer or NULL; filled when non-NULL.
  * The call synchronises once after the first sweep (and once more when rows
- * need the FP32 re-sweep) to size the re-sweep of uncertified rows.  With
+ * need the re-sweep) to size the re-sweep of uncertified rows.  With
  * the contraction streamed, rows the FP32 sweep cannot certify get their
  * exact FP64 values in row panels (at most 256 MiB of workspace each).
  * Non-finite V or psi are reported as GMGM_E_DOMAIN by the next
@@ -146,7 +149,7 @@ gmgm_status gmgm_recompose_topk(gmgm_ctx_t ctx, int64_t n, int64_t r, const floa
  * are reduced until it does, and a call whose workspace still exceeds the
  * array is rejected with GMGM_E_SHAPE before anything is launched (BF16,
  * r = 100: n = 100000 fits, n = 1000000 does not).  Rows the first sweep
- * cannot certify are re-swept in FP32 when that sweep's buffers fit in what
+ * cannot certify are re-swept (as above) when that sweep's buffers fit in what
  * is left of the array, else scanned exactly (the result is the same).  Every
  * call on a device shares that device's array, which keeps the last call's
  * contents (what must start at zero is cleared by each call): calls that
@@ -264,7 +267,8 @@ gmgm_status gmgm_gram(gmgm_ctx_t ctx, int64_t n, int64_t p, int64_t nnz, const i
  *               (row <= column) is read.
  *   evals       p FP64 (device), descending.
  *   evecs       p x p FP64 (device), column-major: column j (evecs[j p .. j p + p))
- *               is the unit eigenvector of evals[j].
+ *               is the unit eigenvector of evals[j]; NULL computes the
+ *               eigenvalues only (faster: no back-transformation).
  *   rank_out    host, or NULL: numerical rank #{j : evals[j] > p 2^-52 evals[0]}.
  * Uses rocSOLVER's divide-and-conquer solver on an FP64 copy.  Synchronises.
  * GMGM_E_DOMAIN for non-finite G, GMGM_E_NOCONV if the solver reports failure.

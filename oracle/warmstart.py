@@ -25,7 +25,11 @@ start).  The paper does not fix this component; the reading implemented here:
 * Optimiser: AdamW (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay
   applied as p -= lr (m_hat / (sqrt(v_hat) + eps) + wd p)).
 
-Everything here is FP64 NumPy written from those definitions.
+Everything here is FP64 NumPy written from those definitions.  The network
+also runs in a BF16-weight mode (``low=True``): the two operands of every
+matrix product, forward and backward, are rounded to BF16 (from their FP32
+value, nearest even) and the products summed in full precision; parameters,
+biases, activations and the optimiser stay in full precision.
 """
 from __future__ import annotations
 
@@ -96,6 +100,22 @@ def apply(curves, Ec, Eg):
             np.exp(_curve_at(curves[BINS:], Eg.size)) / Eg)
 
 
+def bf16(x):
+    """Operands of the BF16-weight mode: a value as FP32, then rounded to the
+    nearest BF16 (8 significant bits, ties to even), returned as FP64."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    hi, lo = b >> 16, b & 0xFFFF
+    up = (lo > 0x8000) | ((lo == 0x8000) & ((hi & 1) == 1))
+    hi = (hi + up.astype(np.uint64)) & 0xFFFF
+    return (hi << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _mm(a, b, low):
+    """a @ b, with both operands rounded to BF16 in the BF16-weight mode."""
+    return bf16(a) @ bf16(b) if low else a @ b
+
+
 def silu(z):
     return z / (1.0 + np.exp(-z))
 
@@ -105,39 +125,43 @@ def silu_grad(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(theta, X, cache=False):
+def forward(theta, X, cache=False, low=False):
+    """The network; low=True is the BF16-weight mode (every product's operands
+    rounded to BF16, the rest in full precision)."""
     P = unpack(theta)
     X = np.asarray(X, dtype=np.float64)
-    Z1 = X @ P["W1"].T + P["b1"]
+    Z1 = _mm(X, P["W1"].T, low) + P["b1"]
     H1 = silu(Z1)
-    Z2 = H1 @ P["W2"].T + P["b2"]
+    Z2 = _mm(H1, P["W2"].T, low) + P["b2"]
     H2 = silu(Z2)
-    Y = H2 @ P["W3"].T + P["b3"]
+    Y = _mm(H2, P["W3"].T, low) + P["b3"]
     if cache:
         return Y, (X, Z1, H1, Z2, H2)
     return Y
 
 
-def loss(theta, X, T, mask=None):
-    Y = forward(theta, X)
+def loss(theta, X, T, mask=None, low=False):
+    Y = forward(theta, X, low=low)
     M = np.ones_like(Y) if mask is None else np.asarray(mask, np.float64)
     return float(np.sum(M * (Y - T) ** 2) / np.sum(M))
 
 
-def loss_and_grad(theta, X, T, mask=None):
-    """Loss and its gradient with respect to the flat parameter vector (chain rule)."""
+def loss_and_grad(theta, X, T, mask=None, low=False):
+    """Loss and its gradient with respect to the flat parameter vector (chain
+    rule); low=True rounds the operands of every product, forward and
+    backward, to BF16."""
     P = unpack(theta)
-    Y, (X, Z1, H1, Z2, H2) = forward(theta, X, cache=True)
+    Y, (X, Z1, H1, Z2, H2) = forward(theta, X, cache=True, low=low)
     M = np.ones_like(Y) if mask is None else np.asarray(mask, np.float64)
     msum = np.sum(M)
     L = float(np.sum(M * (Y - T) ** 2) / msum)
     dY = 2.0 * M * (Y - T) / msum
-    g = {"W3": dY.T @ H2, "b3": dY.sum(axis=0)}
-    dZ2 = (dY @ P["W3"]) * silu_grad(Z2)
-    g["W2"] = dZ2.T @ H1
+    g = {"W3": _mm(dY.T, H2, low), "b3": dY.sum(axis=0)}
+    dZ2 = _mm(dY, P["W3"], low) * silu_grad(Z2)
+    g["W2"] = _mm(dZ2.T, H1, low)
     g["b2"] = dZ2.sum(axis=0)
-    dZ1 = (dZ2 @ P["W2"]) * silu_grad(Z1)
-    g["W1"] = dZ1.T @ X
+    dZ1 = _mm(dZ2, P["W2"], low) * silu_grad(Z1)
+    g["W1"] = _mm(dZ1.T, X, low)
     g["b1"] = dZ1.sum(axis=0)
     return L, pack(g)
 

@@ -427,19 +427,20 @@ def gram(row_ptr, col, val, n: int, p: int, out=None, check: bool = True, shift=
     return G
 
 
-def eigh_small(G):
+def eigh_small(G, vectors: bool = True):
     """(evals descending, evecs column-major as a (p, p) tensor whose ROW j is
-    eigenvector j, numerical rank) of the symmetric FP32 Gram; see gmgm_eigh_small."""
+    eigenvector j -- None with vectors=False --, numerical rank) of the
+    symmetric FP32 Gram; see gmgm_eigh_small."""
     import torch
     if not (G.is_cuda and G.dtype == torch.float32 and G.dim() == 2 and G.shape[0] == G.shape[1]
             and G.is_contiguous()):
         raise TypeError("G must be a contiguous square float32 device tensor")
     p = G.shape[0]
     w = torch.empty(p, dtype=torch.float64, device=G.device)
-    Vt = torch.empty(p, p, dtype=torch.float64, device=G.device)
+    Vt = torch.empty(p, p, dtype=torch.float64, device=G.device) if vectors else None
     rank = _I64()
     c = context(G.device.index)
-    _check(c, load().gmgm_eigh_small(c, p, _ptr(G), _ptr(w), _ptr(Vt), ctypes.byref(rank)))
+    _check(c, load().gmgm_eigh_small(c, p, _ptr(G), _ptr(w), _ptr(Vt) if vectors else None, ctypes.byref(rank)))
     return w, Vt, rank.value
 
 

@@ -39,6 +39,12 @@ __global__ void reorder_kernel(const double* __restrict__ A, const double* __res
   if (blockIdx.x == 0 && threadIdx.x == 0) evals[j] = w[p - 1 - j];
 }
 
+// evals_desc[j] = w[p-1-j] (no eigenvectors)
+__global__ void reorder_values_kernel(const double* __restrict__ w, int64_t p, double* __restrict__ evals) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j < p) evals[j] = w[p - 1 - j];
+}
+
 // out[0] = #{j : evals[j] > p 2^-52 evals[0]}
 __global__ void rank_kernel(const double* __restrict__ evals, int64_t p, long long* __restrict__ out) {
   const double thr = (double)p * 0x1p-52 * evals[0];
@@ -63,7 +69,7 @@ extern "C" gmgm_status gmgm_eigh_small(gmgm_ctx_t c, int64_t p, const float* G, 
                                        double* evecs, int64_t* rank_out) {
   GMGM_CHECK_CTX(c);
   if (p < 1 || p > 46340) return set_err(c, GMGM_E_SHAPE, "p must be in [1, 46340] (got %lld)", (long long)p);
-  if (!G || !evals || !evecs) return set_err(c, GMGM_E_ARG, "null pointer argument");
+  if (!G || !evals) return set_err(c, GMGM_E_ARG, "null pointer argument");
   GMGM_HIP(c, hipSetDevice(c->device));
   hipStream_t st = c->stream;
   void* hv;
@@ -83,13 +89,17 @@ extern "C" gmgm_status gmgm_eigh_small(gmgm_ctx_t c, int64_t p, const float* G, 
   // non-finite input would make the eigensolver's result meaningless: stop here
   GMGM_TRY(gmgm_sync(c));
   hipEvent_t ev = timing_start(c);
-  const rocblas_status rs = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)p, A,
-                                             (rocblas_int)p, w, e, info);
+  // eigenvalues only when no eigenvector output is given
+  const rocblas_status rs = rocsolver_dsyevd(h, evecs ? rocblas_evect_original : rocblas_evect_none,
+                                             rocblas_fill_lower, (rocblas_int)p, A, (rocblas_int)p, w, e, info);
   timing_stop(c, ev);
   if (rs != rocblas_status_success)
     return set_err(c, GMGM_E_HIP, "rocsolver_dsyevd failed with status %d", (int)rs);
-  hipLaunchKernelGGL(reorder_kernel, dim3((unsigned)std::min<int64_t>(64, (p + 255) / 256), (unsigned)p), dim3(256),
-                     0, st, A, w, p, evals, evecs);
+  if (evecs)
+    hipLaunchKernelGGL(reorder_kernel, dim3((unsigned)std::min<int64_t>(64, (p + 255) / 256), (unsigned)p),
+                       dim3(256), 0, st, A, w, p, evals, evecs);
+  else
+    hipLaunchKernelGGL(reorder_values_kernel, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, st, w, p, evals);
   hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(1024), 0, st, evals, p, rk);
   int hinfo = 0;
   long long hrank = 0;

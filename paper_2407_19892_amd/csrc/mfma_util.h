@@ -8,14 +8,23 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 
-// Operand precisions of the recomposition sweep.
-enum : int { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
+// Operand precisions of the recomposition sweep.  P_BF16X3 carries each FP32
+// operand as a BF16 pair x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) and
+// forms hi*hi + hi*lo + lo*hi with three BF16 MFMAs per K step (internal: the
+// re-sweep of rows a BF16 / FP8 sweep could not certify).
+enum : int { P_F32 = 0, P_BF16 = 1, P_FP8 = 2, P_BF16X3 = 3 };
 
 // Elements of one row held in one 16-byte operand chunk.
-__host__ __device__ constexpr int chunk_elems(int prec) { return prec == P_F32 ? 4 : prec == P_BF16 ? 8 : 16; }
+__host__ __device__ constexpr int chunk_elems(int prec) { return prec == P_F32 ? 4 : prec == P_FP8 ? 16 : 8; }
 // Padded contraction length: a multiple of the K of 4 f32 MFMAs (8), one bf16 MFMA (16)
 // or one f8f6f4 MFMA (64).
-__host__ __device__ constexpr int k_align(int prec) { return prec == P_F32 ? 8 : prec == P_BF16 ? 16 : 64; }
+__host__ __device__ constexpr int k_align(int prec) { return prec == P_F32 ? 8 : prec == P_FP8 ? 64 : 16; }
+// 16-byte chunks per lane per 32-row tile: two lanes share a row; the split
+// BF16 form holds the high parts in units [0, kpad/16) and the low parts of
+// the same k in units [kpad/16, kpad/8).
+__host__ __device__ constexpr int units_for(int prec, int kpad) {
+  return prec == P_BF16X3 ? kpad / 8 : kpad / chunk_elems(prec) / 2;
+}
 
 // 32x32 MFMA accumulator layout: lane l, register v holds
 //   row  = 8 * (v / 4) + 4 * (l / 32) + (v % 4),   col = l % 32
@@ -26,11 +35,12 @@ __host__ __device__ constexpr int acc_row(int v, int half) { return 8 * (v / 4) 
 // contiguous k range [k0, k0 + chunk_elems) with
 //   f32 : u = group g (4 MFMAs of K=2): k0 = 8 g + 4 half        (MFMA 4g+q uses element q)
 //   bf16: u = MFMA s (K=16):            k0 = 16 s + 8 half
+//         (split form: unit s + kpad/16 holds the low parts of unit s)
 //   fp8 : u = 2 s + c, MFMA s (K=64):   k0 = 64 s + 32 half + 16 c
 // A and B operands use the same mapping, so each MFMA pairs equal k on both sides.
 __host__ __device__ constexpr int chunk_k0(int prec, int u, int half) {
   return prec == P_F32 ? 8 * u + 4 * half
-       : prec == P_BF16 ? 16 * u + 8 * half
+       : prec != P_FP8 ? 16 * u + 8 * half
                         : 64 * (u / 2) + 32 * half + 16 * (u % 2);
 }
 

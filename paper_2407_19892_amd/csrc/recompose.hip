@@ -11,7 +11,9 @@
 //   finalize  one wave per row: rescore the candidates exactly (FP64), take
 //             the top k, certify that no column outside the candidates can
 //             beat the k-th with the precision's rounding bound, emit CSR
-//   fallback  rows that fail the certificate: exact FP64 scan of the whole row
+//   re-sweep  rows that fail the certificate: the sweep again over their rows
+//             with finer operands (FP32, or split BF16 after a BF16 / FP8 sweep)
+//   fallback  rows that fail again: exact FP64 scan of the whole row
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -134,7 +136,7 @@ __global__ void repack_kernel(const float* __restrict__ V, const double* __restr
   const int k0 = ch * ECH;
   int u, h;
   if (PREC == P_F32) { u = k0 / 8; h = (k0 / 4) & 1; }
-  else if (PREC == P_BF16) { u = k0 / 16; h = (k0 / 8) & 1; }
+  else if (PREC == P_BF16 || PREC == P_BF16X3) { u = k0 / 16; h = (k0 / 8) & 1; }
   else { u = 2 * (k0 / 64) + ((k0 / 16) & 1); h = (k0 / 32) & 1; }
   float x[ECH];
 #pragma unroll
@@ -147,16 +149,23 @@ __global__ void repack_kernel(const float* __restrict__ V, const double* __restr
     }
     x[e] = v;
   }
-  u32x4 o;
+  u32x4 o, olo = u32x4{0, 0, 0, 0};
   if (PREC == P_F32) {
     o = u32x4{__float_as_uint(x[0]), __float_as_uint(x[1]), __float_as_uint(x[2]),
               __float_as_uint(x[3])};
-  } else if (PREC == P_BF16) {
-    unsigned q[4];
+  } else if (PREC == P_BF16 || PREC == P_BF16X3) {
+    unsigned q[4], ql[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      q[e] = (unsigned)f32_to_bf16_bits(x[2 * e]) | ((unsigned)f32_to_bf16_bits(x[2 * e + 1]) << 16);
+    for (int e = 0; e < 4; ++e) {
+      const uint16_t h0 = f32_to_bf16_bits(x[2 * e]), h1 = f32_to_bf16_bits(x[2 * e + 1]);
+      q[e] = (unsigned)h0 | ((unsigned)h1 << 16);
+      // x - hi is exact in FP32; its BF16 rounding is the low part
+      const float r0 = x[2 * e] - __uint_as_float((unsigned)h0 << 16);
+      const float r1 = x[2 * e + 1] - __uint_as_float((unsigned)h1 << 16);
+      ql[e] = (unsigned)f32_to_bf16_bits(r0) | ((unsigned)f32_to_bf16_bits(r1) << 16);
+    }
     o = u32x4{q[0], q[1], q[2], q[3]};
+    olo = u32x4{ql[0], ql[1], ql[2], ql[3]};
   } else {
     const int sc = exp_per_tile ? exps[w / 32] : exps[w];
     unsigned q[4];
@@ -174,7 +183,13 @@ __global__ void repack_kernel(const float* __restrict__ V, const double* __restr
     o = u32x4{q[0], q[1], q[2], q[3]};
   }
   const int64_t tile = w / 32;
-  out[(tile * units + u) * 64 + (w % 32) + 32 * h] = o;
+  if (PREC == P_BF16X3) {
+    // units: the high parts, then the low parts
+    out[(tile * 2 * units + u) * 64 + (w % 32) + 32 * h] = o;
+    out[(tile * 2 * units + units + u) * 64 + (w % 32) + 32 * h] = olo;
+  } else {
+    out[(tile * units + u) * 64 + (w % 32) + 32 * h] = o;
+  }
 }
 
 // ------------------------------------------------------------------ finalize
@@ -515,7 +530,7 @@ int kpad_for(int prec, int r) {
   static const int f32[] = {32, 64, 104, 128};
   static const int bf16[] = {32, 64, 112, 128};
   static const int fp8[] = {64, 128};
-  const int* t = prec == P_F32 ? f32 : prec == P_BF16 ? bf16 : fp8;
+  const int* t = prec == P_F32 ? f32 : prec == P_FP8 ? fp8 : bf16;
   int cnt = prec == P_FP8 ? 2 : 4;
   for (int q = 0; q < cnt; ++q)
     if (t[q] >= r) return t[q];
@@ -529,6 +544,24 @@ SweepFn pick_sweep(int prec, int kpad, int C) {
 }
 
 
+// Split BF16 (x = hi + lo + e, hi = bf16(x), lo = bf16(x - hi)):
+// |lo| <= d (1 + d) |x|, |e| <= d^2 |x|, |hi| <= (1 + d) |x| with d = 2^-8.
+// x y - (hi_x hi_y + hi_x lo_y + lo_x hi_y) = hi_x e_y + lo_x lo_y + lo_x e_y + e_x y,
+// at most d^2 ((1 + d) + (1 + d)^2 + d (1 + d) + 1) |x||y|; the three products
+// are exact in FP32 and sum (in 3 K + 1 accumulation steps) to at most
+// (1 + d)^2 (1 + 2 d (1 + d)) |x||y| in magnitude.
+static double cprec_split_bf16(int kpad) {
+  const double u32 = std::ldexp(1.0, -24);
+  const double uacc = std::ldexp(1.0, -23);
+  const double d = std::ldexp(1.0, -8);
+  const double K = 3.0 * kpad + 1;
+  const double gam = K * uacc / (1.0 - K * uacc);
+  const double drop = d * d * ((1 + d) + (1 + d) * (1 + d) + d * (1 + d) + 1);
+  const double mag = (1 + d) * (1 + d) * (1 + 2 * d * (1 + d));
+  const double c = (1 + u32) * (1 + drop + mag * gam) - 1;
+  return c * (1 + 1e-6) + 1e-12;
+}
+
 // Rounding bound c with |Psi~_ij - Psi_ij| <= c ||W_i||_2 max_j ||V_j||_2 (see header).
 // Operands: a format keeping p significant bits rounds to nearest with relative
 // error at most 2^-p (FP32 p = 24, BF16 p = 8, FP8 e4m3 p = 4, plus e4m3's
@@ -539,6 +572,7 @@ SweepFn pick_sweep(int prec, int kpad, int C) {
 // which also covers truncating adders.  Cauchy-Schwarz turns the elementwise
 // bound sum_k |W_ik||V_jk| into ||W_i|| ||V_j||.
 double cprec_for(int prec, int kpad) {
+  if (prec == P_BF16X3) return cprec_split_bf16(kpad);
   const double u32 = std::ldexp(1.0, -24);     // FP32 rounding of W = V psi
   const double uacc = std::ldexp(1.0, -23);    // one FP32 ulp per accumulation step
   const double K = kpad + 1;
@@ -561,6 +595,7 @@ double cprec_for(int prec, int kpad) {
   }
   return c * (1 + 1e-6) + 1e-12;
 }
+
 
 // Split the columns so that the grid has about `target` workgroups, keeping
 // at least two LDS stages per split.
@@ -1136,16 +1171,19 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
   GMGM_HIP(c, hipGetLastError());
   double flops = 2.0 * (double)w_rows * 32.0 * n_vtiles * kpad;
 
-  // ---- stage B: rows stage A could not certify are re-swept with FP32 operands
+  // ---- stage B: rows stage A could not certify are re-swept with finer operands
   int h1 = 0, h2 = 0;
   GMGM_HIP(c, hipMemcpyAsync(&h1, cnt1, 4, hipMemcpyDeviceToHost, st));
   GMGM_HIP(c, hipStreamSynchronize(st));
   if (h1 > 0) {
+    // FP32 operands after an FP32 sweep; after a BF16 / FP8 sweep split BF16
+    // (three BF16 MFMAs per K step, about 4x FP32's rounding bound)
     const int CB = k <= 12 ? 16 : 32;
-    const int kpadB = kpad_for(P_F32, (int)r);
-    const int unitsB = kpadB / chunk_elems(P_F32) / 2;
-    SweepFn sweepB = pick_sweep(P_F32, kpadB, CB);
-    const int TIB = ti_for(P_F32, CB);
+    const int precB = prec == P_F32 ? P_F32 : P_BF16X3;
+    const int kpadB = kpad_for(precB, (int)r);
+    const int unitsB = units_for(precB, kpadB);
+    SweepFn sweepB = precB == P_F32 ? pick_sweep(P_F32, kpadB, CB) : pick_sweep_bf16x3(kpadB, CB);
+    const int TIB = ti_for(precB, CB);
     const int64_t wtB = ceil_div(h1, 32);
     const int64_t gxB = ceil_div(wtB, (int64_t)SW_WAVES * TIB);
     const int SB = pick_splits(gxB, n_vtiles, 64, 1024);
@@ -1154,6 +1192,7 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
     const int nsubB = sweep_nsub(TIB);
     void* vpb = nullptr;
     gmgm_status sB = stage_buffers(c, WS_WP2, WS_CAND2, wtB, unitsB, h1, SB, nsubB, CB, &B);
+    if (sB == GMGM_OK && !sweepB) sB = set_err(c, GMGM_E_SHAPE, "no re-sweep variant for r = %lld", (long long)r);
     if (sB == GMGM_OK && !(prec == P_F32 && kpadB == kpad))
       sB = ws_get(c, WS_VP2, (size_t)n_vtiles * unitsB * 64 * 16, &vpb);
     if (sB != GMGM_OK) {
@@ -1180,15 +1219,16 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
       B.vp = A.vp;
     } else {
       B.vp = (const u32x4*)vpb;
-      const int64_t tv = (int64_t)n_vtiles * 32 * (kpadB / 4);
-      hipLaunchKernelGGL(repack_kernel<P_F32>, dim3((unsigned)ceil_div(tv, 256)), dim3(256), 0, st, V,
-                         psi, (int64_t)0, n, (int64_t)n_vtiles * 32, (int)r, kpadB, false, ev, true,
-                         (const int*)nullptr, (const int*)nullptr, (u32x4*)vpb);
+      const int64_t tv = (int64_t)n_vtiles * 32 * (kpadB / chunk_elems(precB));
+      hipLaunchKernelGGL(precB == P_F32 ? repack_kernel<P_F32> : repack_kernel<P_BF16X3>,
+                         dim3((unsigned)ceil_div(tv, 256)), dim3(256), 0, st, V, psi, (int64_t)0, n,
+                         (int64_t)n_vtiles * 32, (int)r, kpadB, false, ev, true, (const int*)nullptr,
+                         (const int*)nullptr, (u32x4*)vpb);
     }
-    const int64_t twB = wtB * 32 * (kpadB / 4);
-    hipLaunchKernelGGL(repack_kernel<P_F32>, dim3((unsigned)ceil_div(twB, 256)), dim3(256), 0, st, V,
-                       psi, (int64_t)0, n, wtB * 32, (int)r, kpadB, true, ew, false, (const int*)list1,
-                       (const int*)cnt1, (u32x4*)B.wp);
+    const int64_t twB = wtB * 32 * (kpadB / chunk_elems(precB));
+    hipLaunchKernelGGL(precB == P_F32 ? repack_kernel<P_F32> : repack_kernel<P_BF16X3>,
+                       dim3((unsigned)ceil_div(twB, 256)), dim3(256), 0, st, V, psi, (int64_t)0, n, wtB * 32,
+                       (int)r, kpadB, true, ew, false, (const int*)list1, (const int*)cnt1, (u32x4*)B.wp);
     SweepArgs sb = sa;
     sb.Vp = B.vp;
     sb.Wp = B.wp;
@@ -1199,7 +1239,7 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
     sb.n_wtiles = (int)wtB;
     sb.S = SB;
     sb.tiles_per_split = tpsB;
-    sb.cprec = cprec_for(P_F32, kpadB);
+    sb.cprec = cprec_for(precB, kpadB);
     sweepB<<<dim3((unsigned)gxB, (unsigned)SB), dim3(SW_THREADS), 0, st>>>(sb);
     FinalArgs fb = fa;
     fb.cval = B.cval;
@@ -1209,13 +1249,13 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
     fb.nsub = nsubB;
     fb.row_list = list1;
     fb.row_count = cnt1;
-    fb.cprec = cprec_for(P_F32, kpadB);
+    fb.cprec = cprec_for(precB, kpadB);
     fb.fail_list = list2;
     fb.fail_count = cnt2;
     fb.counters = stats ? counters + 2 : nullptr;   // stage-B candidates are not counted with stage A's
     hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)ceil_div(h1, 4)), dim3(256), 0, st, fb);
     GMGM_HIP(c, hipGetLastError());
-    flops += 2.0 * (double)wtB * 32.0 * n_vtiles * 32.0 * kpadB;
+    flops += (precB == P_F32 ? 2.0 : 6.0) * (double)wtB * 32.0 * n_vtiles * 32.0 * kpadB;
     GMGM_HIP(c, hipMemcpyAsync(&h2, cnt2, 4, hipMemcpyDeviceToHost, st));
     GMGM_HIP(c, hipStreamSynchronize(st));
     // ---- stage C: rows still uncertified (exact ties at the boundary, non-finite inputs)

@@ -64,9 +64,19 @@ struct SweepArgs {
   const long long* toff;  // threshold mode, listed rows: candidate offsets per slot (null: slot * capt)
 };
 
-template <int PREC>
+// HALF: split BF16 form only, the unit offset of the low parts (kpad / 16).
+template <int PREC, int HALF = 0>
 __device__ inline v16f mfma_chunk(const u32x4* a, const u32x4* b, v16f acc, int u) {
-  if constexpr (PREC == P_F32) {
+  if constexpr (PREC == P_BF16X3) {
+    if (u < HALF) {
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a[u]),
+                                                   __builtin_bit_cast(v8bf, b[u]), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a[u]),
+                                                   __builtin_bit_cast(v8bf, b[u + HALF]), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a[u + HALF]),
+                                                   __builtin_bit_cast(v8bf, b[u]), acc, 0, 0, 0);
+    }
+  } else if constexpr (PREC == P_F32) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[u][q]), __uint_as_float(b[u][q]),
@@ -334,11 +344,13 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
 #pragma unroll
         for (int u = 0; u < UNITS; ++u)
 #pragma unroll
-          for (int t = 0; t < TI; ++t) acc[t] = mfma_chunk<PREC>(av, b[t], acc[t], u);
+          for (int t = 0; t < TI; ++t) acc[t] = mfma_chunk<PREC, UNITS / 2>(av, b[t], acc[t], u);
         // issue every operand read of the tile before its MFMAs (else the
         // scheduler reuses one register and waits on each read in turn)
+        constexpr int MF = PREC == P_F32 ? 4 * UNITS : PREC == P_FP8 ? UNITS / 2
+                         : PREC == P_BF16X3 ? 3 * (UNITS / 2) : UNITS;
         __builtin_amdgcn_sched_group_barrier(0x100, UNITS, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, UNITS * TI * (PREC == P_F32 ? 4 : 1) / (PREC == P_FP8 ? 2 : 1), 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, MF * TI, 0);
 
         const int j0 = jt * 32;
         // tiles holding the diagonal or the end of the columns exclude some values
@@ -525,10 +537,11 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
 typedef void (*SweepFn)(SweepArgs);
 
 // Row tiles per wave: two for the short BF16 / FP8 operands (each lane then
-// owns one full row), one for FP32 operands (lanes keep half rows); this is
-// the register budget of the B operands and lists at 2 waves per SIMD.
+// owns one full row), one for FP32 and split BF16 operands (lanes keep half
+// rows); this is the register budget of the B operands and lists at 2 waves
+// per SIMD.
 __host__ __device__ constexpr int ti_for(int prec, int C) {
-  return (prec != P_F32) ? 2 : 1;
+  return (prec == P_BF16 || prec == P_FP8) ? 2 : 1;
 }
 
 // One translation unit per (precision, list length) keeps the build parallel.
@@ -538,6 +551,7 @@ SweepFn pick_sweep_bf16_c16(int kpad);
 SweepFn pick_sweep_bf16_c32(int kpad);
 SweepFn pick_sweep_fp8_c16(int kpad);
 SweepFn pick_sweep_fp8_c32(int kpad);
+SweepFn pick_sweep_bf16x3(int kpad, int C);   // split BF16 re-sweep
 SweepFn pick_sweep_thr(int prec, int kpad);   // threshold mode
 
 }  // namespace gmgm_rc

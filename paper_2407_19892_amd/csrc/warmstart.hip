@@ -8,14 +8,18 @@
 // hidden layers, FP32 parameters W1 b1 W2 b2 W3 b3 (row-major, flat).
 // Outputs: two 512-bin curves of log(lambda E); index i of an axis reads the
 // curve at u_i = (i + 1/2) 512 / r - 1/2.  Loss: masked mean squared error;
-// optimiser: AdamW.  GEMMs are LDS-tiled FP32 FMA (the matrices are small:
-// the step is latency-bound, not compute-bound); every reduction has a fixed
-// order, so a training step is deterministic.
+// optimiser: AdamW.  Two precisions of the same network: the gmgm_ws_* calls
+// run LDS-tiled FP32 FMA products (the reference mode), the gmgm_warmstart_*
+// calls BF16 operands on the matrix cores with FP32 accumulation and FP32
+// master weights (every product's two operands are rounded to BF16 as they are
+// staged).  Every reduction has a fixed order, so a training step is
+// deterministic.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
 #include "gmgm_internal.h"
+#include "mfma_util.h"
 
 namespace gmgm_ws {
 
@@ -127,6 +131,59 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, const fl
       const int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
       if (gm < M && gn < N) C[(size_t)gm * ldc + gn] = acc[i][j] + (bias ? bias[gn] : 0.f);
     }
+}
+
+// The same product with BF16 operands on the matrix cores: op(A) and op(B)
+// are rounded to BF16 (nearest even) as they are staged into LDS, products
+// accumulate in FP32 (V_MFMA_F32_32X32X16_BF16), the bias is added in FP32.
+// 64 x 64 output tile per workgroup, 4 waves of 32 x 32; the contraction in
+// steps of 32 (two MFMAs).  LDS rows hold 32 k (+ 8 of padding) of one m or
+// n, so that each lane reads its 8 consecutive k as one 16-byte load.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                        const float* __restrict__ B, int ldb,
+                                                        const float* __restrict__ bias, float* __restrict__ C,
+                                                        int ldc) {
+  constexpr int KT = 32, LDK = KT + 8;
+  __shared__ __align__(16) uint16_t As[64][LDK], Bs[64][LDK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  v16f acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  for (int k0 = 0; k0 < K; k0 += KT) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = tid + 256 * u;              // 0..2047 over a 64 x 32 tile of each operand
+      int mm, kk;
+      if (TA) { kk = q >> 6; mm = q & 63; } else { mm = q >> 5; kk = q & 31; }
+      int nn, kb;
+      if (TB) { nn = q >> 5; kb = q & 31; } else { kb = q >> 6; nn = q & 63; }
+      const int gm = m0 + mm, gk = k0 + kk, gn = n0 + nn, gkb = k0 + kb;
+      float av = 0.f, bv = 0.f;
+      if (gm < M && gk < K) av = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+      if (gn < N && gkb < K) bv = TB ? B[(size_t)gn * ldb + gkb] : B[(size_t)gkb * ldb + gn];
+      As[mm][kk] = f32_to_bf16_bits(av);
+      Bs[nn][kb] = f32_to_bf16_bits(bv);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KT / 16; ++s) {
+      const int kq = 16 * s + 8 * (lane >> 5);
+      const v8bf a = __builtin_bit_cast(v8bf, *(const uint4*)&As[32 * wm + (lane & 31)][kq]);
+      const v8bf b = __builtin_bit_cast(v8bf, *(const uint4*)&Bs[32 * wn + (lane & 31)][kq]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int gm = m0 + 32 * wm + acc_row(v, lane >> 5);
+    const int gn = n0 + 32 * wn + (lane & 31);
+    if (gm < M && gn < N) C[(size_t)gm * ldc + gn] = acc[v] + (bias ? bias[gn] : 0.f);
+  }
 }
 
 __device__ inline float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
@@ -266,11 +323,17 @@ __global__ void init_kernel(float* __restrict__ p, uint64_t seed) {
 
 inline unsigned nb(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
+// bf16 selects the matrix-core product with BF16 operands (the network's
+// BF16-weight mode); otherwise FP32 FMA tiles.
 template <bool TA, bool TB>
-void gemm(hipStream_t st, int M, int N, int K, const float* A, int lda, const float* B, int ldb, const float* bias,
-          float* C, int ldc) {
-  hipLaunchKernelGGL((gemm_kernel<TA, TB>), dim3(nb(N, 64), nb(M, 64)), dim3(256), 0, st, M, N, K, A, lda, B, ldb,
-                     bias, C, ldc);
+void gemm(hipStream_t st, bool bf16, int M, int N, int K, const float* A, int lda, const float* B, int ldb,
+          const float* bias, float* C, int ldc) {
+  if (bf16)
+    hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB>), dim3(nb(N, 64), nb(M, 64)), dim3(256), 0, st, M, N, K, A, lda,
+                       B, ldb, bias, C, ldc);
+  else
+    hipLaunchKernelGGL((gemm_kernel<TA, TB>), dim3(nb(N, 64), nb(M, 64)), dim3(256), 0, st, M, N, K, A, lda, B,
+                       ldb, bias, C, ldc);
 }
 
 struct Acts {
@@ -291,12 +354,12 @@ gmgm_status acts(gmgm_ctx* c, int batch, Acts* a, float** extra, int64_t extra_f
   return GMGM_OK;
 }
 
-void forward(hipStream_t st, const float* P, int B, const float* X, const Acts& a, float* Y) {
-  gemm<false, true>(st, B, D_H, D_IN, X, D_IN, P + OFF_W1, D_IN, P + OFF_B1, a.Z1, D_H);
+void forward(hipStream_t st, bool bf, const float* P, int B, const float* X, const Acts& a, float* Y) {
+  gemm<false, true>(st, bf, B, D_H, D_IN, X, D_IN, P + OFF_W1, D_IN, P + OFF_B1, a.Z1, D_H);
   hipLaunchKernelGGL(silu_kernel, dim3(nb((int64_t)B * D_H)), dim3(256), 0, st, a.Z1, a.H1, (int64_t)B * D_H);
-  gemm<false, true>(st, B, D_H, D_H, a.H1, D_H, P + OFF_W2, D_H, P + OFF_B2, a.Z2, D_H);
+  gemm<false, true>(st, bf, B, D_H, D_H, a.H1, D_H, P + OFF_W2, D_H, P + OFF_B2, a.Z2, D_H);
   hipLaunchKernelGGL(silu_kernel, dim3(nb((int64_t)B * D_H)), dim3(256), 0, st, a.Z2, a.H2, (int64_t)B * D_H);
-  gemm<false, true>(st, B, D_OUT, D_H, a.H2, D_H, P + OFF_W3, D_H, P + OFF_B3, Y, D_OUT);
+  gemm<false, true>(st, bf, B, D_OUT, D_H, a.H2, D_H, P + OFF_W3, D_H, P + OFF_B3, Y, D_OUT);
 }
 
 }  // namespace gmgm_ws
@@ -348,7 +411,7 @@ extern "C" gmgm_status gmgm_ws_forward(gmgm_ctx_t c, const float* params, int32_
   Acts a;
   float* extra;
   GMGM_TRY(acts(c, batch, &a, &extra, 0));
-  forward(c->stream, params, batch, feats, a, out);
+  forward(c->stream, false, params, batch, feats, a, out);
   GMGM_HIP(c, hipGetLastError());
   return GMGM_OK;
 }
@@ -357,7 +420,7 @@ namespace gmgm_ws {
 // One training step: forward, masked MSE, backward, AdamW.  The update count
 // and weight decay come from the host (step >= 1, weight_decay) or, with
 // `state`, from the device header (incremented there).
-static gmgm_status train_impl(gmgm_ctx* c, float* params, float* adam_m, float* adam_v, int64_t step,
+static gmgm_status train_impl(gmgm_ctx* c, bool bf, float* params, float* adam_m, float* adam_v, int64_t step,
                               float weight_decay, OptHeader* state, int32_t batch, const float* feats,
                               const float* target, const float* mask, float lr, double* loss_out,
                               float* grad_out) {
@@ -373,21 +436,21 @@ static gmgm_status train_impl(gmgm_ctx* c, float* params, float* adam_m, float* 
   double* scal = (double*)ws;
   float* bcp = (float*)((char*)ws + 32);
 
-  forward(st, params, B, feats, a, a.Y);
+  forward(st, bf, params, B, feats, a, a.Y);
   hipLaunchKernelGGL(loss_sums_kernel, dim3(1), dim3(1024), 0, st, a.Y, target, mask, nY, scal);
   hipLaunchKernelGGL(loss_grad_kernel, dim3(nb(nY)), dim3(256), 0, st, a.Y, target, mask, nY, scal, dY);
   // layer 3
-  gemm<true, false>(st, D_OUT, D_H, B, dY, D_OUT, a.H2, D_H, nullptr, g + OFF_W3, D_H);
+  gemm<true, false>(st, bf, D_OUT, D_H, B, dY, D_OUT, a.H2, D_H, nullptr, g + OFF_W3, D_H);
   hipLaunchKernelGGL(colsum_kernel, dim3(nb(D_OUT)), dim3(256), 0, st, dY, B, D_OUT, g + OFF_B3);
-  gemm<false, false>(st, B, D_H, D_OUT, dY, D_OUT, params + OFF_W3, D_H, nullptr, dH, D_H);
+  gemm<false, false>(st, bf, B, D_H, D_OUT, dY, D_OUT, params + OFF_W3, D_H, nullptr, dH, D_H);
   hipLaunchKernelGGL(silu_back_kernel, dim3(nb(nH)), dim3(256), 0, st, dH, a.Z2, dZ, nH);
   // layer 2
-  gemm<true, false>(st, D_H, D_H, B, dZ, D_H, a.H1, D_H, nullptr, g + OFF_W2, D_H);
+  gemm<true, false>(st, bf, D_H, D_H, B, dZ, D_H, a.H1, D_H, nullptr, g + OFF_W2, D_H);
   hipLaunchKernelGGL(colsum_kernel, dim3(nb(D_H)), dim3(256), 0, st, dZ, B, D_H, g + OFF_B2);
-  gemm<false, false>(st, B, D_H, D_H, dZ, D_H, params + OFF_W2, D_H, nullptr, dH, D_H);
+  gemm<false, false>(st, bf, B, D_H, D_H, dZ, D_H, params + OFF_W2, D_H, nullptr, dH, D_H);
   hipLaunchKernelGGL(silu_back_kernel, dim3(nb(nH)), dim3(256), 0, st, dH, a.Z1, dZ, nH);
   // layer 1
-  gemm<true, false>(st, D_H, D_IN, B, dZ, D_H, feats, D_IN, nullptr, g + OFF_W1, D_IN);
+  gemm<true, false>(st, bf, D_H, D_IN, B, dZ, D_H, feats, D_IN, nullptr, g + OFF_W1, D_IN);
   hipLaunchKernelGGL(colsum_kernel, dim3(nb(D_H)), dim3(256), 0, st, dZ, B, D_H, g + OFF_B1);
   if (grad_out)
     GMGM_HIP(c, hipMemcpyAsync(grad_out, g, N_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, st));
@@ -418,7 +481,7 @@ extern "C" gmgm_status gmgm_ws_train_step(gmgm_ctx_t c, float* params, float* ad
   if (step < 1 || !(lr >= 0) || !(weight_decay >= 0))
     return set_err(c, GMGM_E_ARG, "need step >= 1, lr >= 0, weight_decay >= 0");
   GMGM_HIP(c, hipSetDevice(c->device));
-  return train_impl(c, params, adam_m, adam_v, step, weight_decay, nullptr, batch, feats, target, mask, lr,
+  return train_impl(c, false, params, adam_m, adam_v, step, weight_decay, nullptr, batch, feats, target, mask, lr,
                     loss_out, grad_out);
 }
 
@@ -438,7 +501,16 @@ extern "C" gmgm_status gmgm_warmstart_state_init(gmgm_ctx_t c, void* opt_state, 
 
 extern "C" gmgm_status gmgm_warmstart_infer(gmgm_ctx_t c, const void* weights, int32_t batch, const float* feats,
                                             float* out) {
-  return gmgm_ws_forward(c, (const float*)weights, batch, feats, out);
+  GMGM_CHECK_CTX(c);
+  if (!weights || !feats || !out) return set_err(c, GMGM_E_ARG, "null pointer argument");
+  if (batch < 1 || batch > MAX_BATCH) return set_err(c, GMGM_E_SHAPE, "batch must be in [1, %d]", MAX_BATCH);
+  GMGM_HIP(c, hipSetDevice(c->device));
+  Acts a;
+  float* extra;
+  GMGM_TRY(acts(c, batch, &a, &extra, 0));
+  forward(c->stream, true, (const float*)weights, batch, feats, a, out);
+  GMGM_HIP(c, hipGetLastError());
+  return GMGM_OK;
 }
 
 extern "C" gmgm_status gmgm_warmstart_train_step(gmgm_ctx_t c, void* weights, void* opt_state, int32_t batch,
@@ -451,7 +523,7 @@ extern "C" gmgm_status gmgm_warmstart_train_step(gmgm_ctx_t c, void* weights, vo
   GMGM_HIP(c, hipSetDevice(c->device));
   char* stt = (char*)opt_state;
   double loss = 0.0;
-  GMGM_TRY(train_impl(c, (float*)weights, (float*)(stt + OPT_M), (float*)(stt + OPT_V), 0, 0.0f,
+  GMGM_TRY(train_impl(c, true, (float*)weights, (float*)(stt + OPT_M), (float*)(stt + OPT_V), 0, 0.0f,
                       (OptHeader*)stt, batch, feats, target, mask, lr, loss_out ? &loss : nullptr, nullptr));
   if (loss_out) *loss_out = (float)loss;
   return GMGM_OK;

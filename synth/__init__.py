@@ -20,6 +20,13 @@ Recipes (all seeded, all reproducible block by block):
   shared rank-8 factor and per-cell noise directions.
 * ``spectrum_proxy`` -- a descending positive spectrum of a p x p Gram matrix
   with a few signal spikes above a Marchenko-Pastur bulk.
+* ``nb_log1p_gpu`` -- the ``nb_log1p`` recipe drawn on the GPU with torch's
+  seeded Philox generator (normals, gamma, Poisson), for the many mid-sized
+  instances of the warm-start training set; not used by any oracle
+  comparison.
+* ``rotating_objects`` -- tensors shaped like the paper's COIL-20 videos:
+  objects of (frames x h x w) whose pixels vary with the frame angle through
+  the first three circular harmonics (a rank-3 image per harmonic) plus noise.
 
 Each row block of ``nb_log1p`` draws from its own Philox stream keyed by
 (seed, block), so any block of rows can be regenerated alone.
@@ -40,6 +47,8 @@ __all__ = [
     "csr_proxy",
     "spectrum_proxy",
     "workload",
+    "rotating_objects",
+    "nb_log1p_gpu",
     "ROW_BLOCK",
 ]
 
@@ -262,3 +271,44 @@ def csr_proxy(n: int, p: int, density: float, seed: int, block: int = 16384, wor
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
     return row_ptr, np.concatenate([q[1] for q in parts]), np.concatenate([q[2] for q in parts])
+
+
+def rotating_objects(n_obj=20, frames=72, h=128, w=128, seed=0, noise=0.05):
+    """List of n_obj float64 arrays (frames x h x w): sum over harmonics q = 1..3
+    and cos / sin of trig(q angle_f) B_q,trig with B a rank-3 h x w image
+    (Gaussian factors, weight 1/q), plus Gaussian noise; angle_f = 2 pi f / frames."""
+    rng = np.random.default_rng(seed)
+    ang = 2 * np.pi * np.arange(frames) / frames
+    out = []
+    for _ in range(n_obj):
+        X = np.zeros((frames, h, w))
+        for q in range(1, 4):
+            for trig in (np.cos, np.sin):
+                B = rng.standard_normal((h, 3)) @ rng.standard_normal((3, w)) / q
+                X += trig(q * ang)[:, None, None] * B[None]
+        X += noise * rng.standard_normal(X.shape)
+        out.append(X)
+    return out
+
+
+def nb_log1p_gpu(n, p, n_clusters, zipf, seed, beta0=0.0, device="cuda"):
+    """X = log1p(NB counts) (n x p, float32, on `device`) of the ``nb_log1p``
+    recipe: log mu = beta0 + 0.5 (A B^T)_ij / sqrt(8) + M[cl(i), j] + g_j, counts
+    Gamma(1/alpha, alpha mu) -> Poisson, drawn from torch's Philox generator
+    seeded with `seed` (cluster labels as in ``cluster_labels``)."""
+    import torch
+    gen = torch.Generator(device=device).manual_seed(int(seed))
+    lab = torch.from_numpy(cluster_labels(n, n_clusters, zipf, seed).astype(np.int64)).to(device)
+    f64 = torch.float64
+    A = torch.randn(n, FACTOR_RANK, generator=gen, device=device, dtype=f64)
+    B = torch.randn(p, FACTOR_RANK, generator=gen, device=device, dtype=f64)
+    M = torch.randn(n_clusters, p, generator=gen, device=device, dtype=f64)
+    g = torch.randn(p, generator=gen, device=device, dtype=f64) * math.sqrt(0.5)
+    mu = torch.exp(beta0 + 0.5 * (A @ B.T) / math.sqrt(FACTOR_RANK) + M[lab] + g[None, :])
+    del A, M
+    shape = torch.full_like(mu, 1.0 / ALPHA)
+    lam = torch._standard_gamma(shape, generator=gen) * (ALPHA * mu)
+    del shape, mu
+    counts = torch.poisson(lam, generator=gen)
+    del lam
+    return torch.log1p(counts).to(torch.float32)

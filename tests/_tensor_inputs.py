@@ -35,18 +35,12 @@ def low_rank_tensor_spectra(shape, rank, seed, noise=0.3):
 
 def coil_like_spectra(n_obj=20, frames=72, h=128, w=128, seed=0, noise=0.05):
     """Returns (E, modalities): E[0] the frame axis, E[1 + 2i] and E[2 + 2i]
-    object i's row and column axes; modality i = (0, 1 + 2i, 2 + 2i)."""
-    rng = np.random.default_rng(seed)
-    ang = 2 * np.pi * np.arange(frames) / frames
+    object i's row and column axes; modality i = (0, 1 + 2i, 2 + 2i).  The
+    tensors come from synth.rotating_objects."""
+    import synth
     G_frame = np.zeros((frames, frames))
     rows, cols = [], []
-    for _ in range(n_obj):
-        X = np.zeros((frames, h, w))
-        for k in range(1, 4):
-            for trig in (np.cos, np.sin):
-                B = rng.standard_normal((h, 3)) @ rng.standard_normal((3, w)) / k
-                X += trig(k * ang)[:, None, None] * B[None]
-        X += noise * rng.standard_normal(X.shape)
+    for X in synth.rotating_objects(n_obj, frames, h, w, seed=seed, noise=noise):
         U = X.reshape(frames, -1)
         G_frame += U @ U.T
         rows.append(_spectrum(np.moveaxis(X, 1, 0).reshape(h, -1)))

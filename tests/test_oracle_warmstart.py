@@ -149,3 +149,47 @@ def test_adamw_alternating_gradient_closed_form():
         mh = m_t / (1 - 0.9 ** t)
         want = want - lr * mh / (np.abs(g) + 1e-8)
         np.testing.assert_allclose(theta, want, rtol=1e-12, atol=1e-15)
+
+
+def test_bf16_rounding_against_the_definition():
+    """The BF16-weight mode's rounding: the nearest value with 8 significant bits
+    (ties to even), from the FP32 value, brute force over a grid."""
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.standard_normal(500) * 10.0 ** rng.integers(-5, 5, 500),
+                        [1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -2.5, 0.0, 1 + 2 ** -9]])
+    got = W.bf16(x)
+    for v, g in zip(x, got):
+        f = float(np.float32(v))
+        if f == 0.0:
+            assert g == 0.0
+            continue
+        e = math.floor(math.log2(abs(f)))
+        ulp = 2.0 ** (e - 7)
+        lo = math.floor(f / ulp) * ulp
+        cands = [lo, lo + ulp]
+        d = [abs(c - f) for c in cands]
+        if d[0] == d[1]:
+            want = cands[0] if round(cands[0] / ulp) % 2 == 0 else cands[1]
+        else:
+            want = cands[int(np.argmin(d))]
+        assert g == want, (v, g, want)
+
+
+def test_bf16_mode_error_is_the_rounding_of_its_operands():
+    """With the inputs and the output weights already BF16 values and the hidden
+    weights zero, the only operand the BF16 mode rounds is the constant hidden
+    row silu(b2): the outputs then differ from the full mode by at most one BF16
+    rounding (2^-8 relative) of it, per output weight row, and do differ."""
+    theta, X, T, _ = _small_problem(5)
+    P = W.unpack(theta)
+    P["W1"][:] = 0
+    P["W2"][:] = 0
+    P["W3"] = W.bf16(P["W3"])
+    th = W.pack(P)
+    Xb = W.bf16(X)
+    h2 = W.silu(P["b2"])
+    Y0 = W.forward(th, Xb)
+    Y1 = W.forward(th, Xb, low=True)
+    bound = 2.0 ** -8 * (np.abs(P["W3"]) @ np.abs(h2))
+    assert np.all(np.abs(Y0 - Y1) <= bound[None, :] * (1 + 1e-12))
+    assert np.max(np.abs(Y0 - Y1)) > 0
