@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "gmgm_internal.h"
@@ -207,6 +209,154 @@ __global__ void __launch_bounds__(256) gram_finish_kernel(const double* __restri
   }
 }
 
+// ------------------------------------------------------------------ sparse path
+// G accumulated straight from the nonzeros: for every row x_r, the products
+// x_ra x_rb of its entries with a <= b are added into 128 x 128 FP64 tiles
+// held in LDS (one workgroup per tile pair (A, B), A <= B, and row split).
+// Work is sum_r nnz_r^2 / 2 products instead of n p^2 / 2 for dense panels.
+// The entries of row r in column block q are [off[q][r], off[q + 1][r])
+// relative to row_ptr[r], which needs strictly increasing columns per row;
+// other rows (unsorted or duplicate columns) take all ordered pairs with
+// global FP64 atomics.
+constexpr int ST = 128;               // sparse tile edge (FP64 tile: 128 KB of LDS)
+constexpr int SP_THREADS = 1024;
+
+// One wave per row of [r0, r0 + rows): block offsets of sorted rows (local
+// row index), zero offsets (no work) for every other row; unsorted rows are
+// listed for the generic kernel, malformed rows reported and skipped.
+__global__ void __launch_bounds__(256) block_offsets_kernel(const int64_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ col,
+                                                            const float* __restrict__ val, int64_t nnz,
+                                                            int64_t p, int64_t r0, int64_t rows, int nb,
+                                                            int* __restrict__ off, int* __restrict__ bad_rows,
+                                                            int* __restrict__ bad_count, int* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= rows) return;
+  const int64_t b = rp[r0 + i], e = rp[r0 + i + 1];
+  auto zero_offsets = [&]() {
+    for (int q = lane; q <= nb; q += 64) off[(size_t)q * rows + i] = 0;
+  };
+  if (b < 0 || e < b || e > nnz || e - b > (int64_t)0x7fffffff) {
+    if (lane == 0) atomicCAS(status, 0, DEV_BADINDEX);
+    zero_offsets();
+    return;
+  }
+  bool badc = false, badv = false, unsorted = false;
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int c = col[t];
+    badc |= c < 0 || c >= p;
+    if (val) badv |= !isfinite(val[t]);
+    if (t > b) unsorted |= c <= col[t - 1];
+  }
+  if (__ballot(badv) && lane == 0) atomicCAS(status, 0, DEV_NONFINITE);
+  if (__ballot(badc)) {
+    if (lane == 0) atomicCAS(status, 0, DEV_BADINDEX);
+    zero_offsets();
+    return;
+  }
+  if (__ballot(unsorted)) {
+    zero_offsets();
+    if (lane == 0) bad_rows[atomicAdd(bad_count, 1)] = (int)(r0 + i);
+    return;
+  }
+  // block q starts at the first entry whose column is >= q * ST
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int bc = col[t] / ST;
+    const int bp = t > b ? col[t - 1] / ST : -1;
+    for (int q = bp + 1; q <= bc; ++q) off[(size_t)q * rows + i] = (int)(t - b);
+  }
+  const int last = e > b ? col[e - 1] / ST : -1;
+  for (int q = last + 1 + lane; q <= nb; q += 64) off[(size_t)q * rows + i] = (int)(e - b);
+}
+
+struct SparseArgs {
+  const int64_t* rp;   // row_ptr of X (global rows)
+  const int32_t* col;
+  const float* val;    // nullptr: all ones
+  const int* off;      // (nb + 1) x rows block offsets of this row chunk
+  int64_t r0, rows;    // the chunk: global rows [r0, r0 + rows)
+  int64_t rows_split;  // rows per split
+  const int2* tiles;   // (A, B), B >= A
+  int64_t pp;          // nb * ST
+  double* P;           // n_split x pp x pp FP64 partials (added to)
+};
+
+__global__ void __launch_bounds__(SP_THREADS) gram_sparse_tile_kernel(SparseArgs a) {
+  __shared__ double t[ST * ST];
+  const int tid = threadIdx.x;
+  const int2 AB = a.tiles[blockIdx.x];
+  const int A = AB.x, B = AB.y;
+  const bool diag = A == B;
+  for (int q = tid; q < ST * ST; q += SP_THREADS) t[q] = 0.0;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.y * a.rows_split;
+  const int64_t hi = lo + a.rows_split < a.rows ? lo + a.rows_split : a.rows;
+  const int* offA0 = a.off + (size_t)A * a.rows;
+  const int* offA1 = offA0 + a.rows;
+  const int* offB0 = a.off + (size_t)B * a.rows;
+  const int* offB1 = offB0 + a.rows;
+  const int cA = A * ST, cB = B * ST;
+  for (int64_t r = lo + tid; r < hi; r += SP_THREADS) {
+    const int a0 = offA0[r], a1 = offA1[r], b0 = offB0[r], b1 = offB1[r];
+    if (a0 >= a1 || b0 >= b1) continue;
+    const int64_t base = a.rp[a.r0 + r];
+    const int32_t* cr = a.col + base;
+    const float* vr = a.val ? a.val + base : nullptr;
+    // eight B entries in registers at a time, every A entry against them
+    for (int j0 = b0; j0 < b1; j0 += 8) {
+      int cb[8];
+      double vb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + u < b1 ? j0 + u : b1 - 1;
+        cb[u] = cr[j] - cB;
+        vb[u] = vr ? (double)vr[j] : 1.0;
+      }
+      const int iend = diag ? (a1 < j0 + 8 ? a1 : j0 + 8) : a1;   // diagonal tile: i <= j
+      for (int i = a0; i < iend; ++i) {
+        const double va = vr ? (double)vr[i] : 1.0;
+        double* trow = t + (cr[i] - cA) * ST;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = j0 + u;
+          if (j < b1 && (!diag || j >= i)) atomicAdd(trow + cb[u], va * vb[u]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double* Pt = a.P + (size_t)blockIdx.y * a.pp * a.pp + (size_t)cA * a.pp + cB;
+  for (int q = tid; q < ST * ST; q += SP_THREADS) {
+    const int x = q / ST, y = q % ST;
+    if (t[q] != 0.0) Pt[(size_t)x * a.pp + y] += t[q];
+  }
+}
+
+// Rows without strictly increasing columns: every ordered pair (i, j) adds
+// x_i x_j to P[c_i][c_j] when c_i <= c_j (so a duplicate column c gets
+// (sum of its values)^2), with global FP64 atomics into partial 0.  One
+// workgroup per listed row.
+__global__ void __launch_bounds__(256) gram_rows_generic_kernel(const int64_t* __restrict__ rp,
+                                                                const int32_t* __restrict__ col,
+                                                                const float* __restrict__ val,
+                                                                const int* __restrict__ list,
+                                                                const int* __restrict__ count, int64_t pp,
+                                                                double* __restrict__ P) {
+  const int cnt = *count;
+  for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
+    const int64_t r = list[q];
+    const int64_t b = rp[r], m = rp[r + 1] - b;
+    for (int64_t x = threadIdx.x; x < m * m; x += blockDim.x) {
+      const int64_t i = b + x / m, j = b + x % m;
+      const int ci = col[i], cj = col[j];
+      if (ci > cj) continue;
+      const double v = (val ? (double)val[i] : 1.0) * (val ? (double)val[j] : 1.0);
+      unsafeAtomicAdd(P + (size_t)ci * pp + cj, v);
+    }
+  }
+}
+
 inline unsigned grid_for(int64_t n, int per_block) {
   const int64_t g = (n + per_block - 1) / per_block;
   return (unsigned)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
@@ -216,6 +366,76 @@ inline unsigned grid_for(int64_t n, int per_block) {
 
 using namespace gmgm_gr;
 
+// Path choice from the shape alone (no synchronisation): estimated time of
+// the dense panels (FP32 MFMA, n p_pad^2 multiply-adds) against the sparse
+// tiles (per tile pair a pass over the row offsets, the entries of both
+// blocks re-read per pair, ~nnz^2 / 2n LDS atomics).  GMGM_GRAM_PATH=dense or
+// =sparse in the environment forces a path.
+static bool gram_use_sparse(int64_t n, int64_t p, int64_t nnz) {
+  if (n >= ((int64_t)1 << 31)) return false;
+  if (const char* e = getenv("GMGM_GRAM_PATH")) {
+    if (!strcmp(e, "dense")) return false;
+    if (!strcmp(e, "sparse")) return true;
+  }
+  const double nb = (double)((p + ST - 1) / ST);
+  const double ppd = (double)((p + GT - 1) / GT * GT);
+  const double t_dense = (double)n * ppd * ppd / 1.18e14;
+  const double pairs = nb * (nb + 1) / 2;
+  const double t_sparse = (pairs * (double)n * 24.0 + (nb + 1) * (double)nnz * 8.0) / 3.0e12 +
+                          (double)nnz * (double)nnz / (2.0 * (double)n) / 1.0e13;
+  return t_sparse < t_dense;
+}
+
+static gmgm_status gram_sparse(gmgm_ctx* c, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                               const int32_t* col, const float* val, const double* zs, const double* cs,
+                               float* G) {
+  hipStream_t st = c->stream;
+  const int nb = (int)((p + ST - 1) / ST);
+  const int64_t pp = (int64_t)nb * ST;
+  const int n_pairs = nb * (nb + 1) / 2;
+  // row chunks: block offsets of at most 1 GiB
+  const int64_t rows_c = std::min<int64_t>(n, std::max<int64_t>(4096, ((int64_t)1 << 30) / (4 * (nb + 1))));
+  // row splits: enough workgroups to cover the chip, >= 4096 rows each, partials <= 8 GiB
+  int n_split = (int)std::min<int64_t>(64, (2048 + n_pairs - 1) / n_pairs);
+  n_split = (int)std::max<int64_t>(1, std::min<int64_t>(n_split, rows_c / 4096));
+  while (n_split > 1 && (double)n_split * pp * pp * 8 > 8.0 * (1 << 30)) n_split--;
+
+  void *wO, *wP, *wT;
+  const size_t off_bytes = ((size_t)(nb + 1) * rows_c * 4 + 255) & ~(size_t)255;
+  GMGM_TRY(ws_get(c, WS_GRAM0, 256 + off_bytes + (size_t)n * 4, &wO));
+  GMGM_TRY(ws_get(c, WS_GRAM1, (size_t)n_split * pp * pp * sizeof(double), &wP));
+  GMGM_TRY(ws_get(c, WS_GRAM2, (size_t)n_pairs * sizeof(int2), &wT));
+  int* bad_count = (int*)wO;
+  int* off = (int*)((char*)wO + 256);
+  int* bad_rows = (int*)((char*)wO + 256 + off_bytes);
+  std::vector<int2> tiles;
+  tiles.reserve(n_pairs);
+  for (int A = 0; A < nb; ++A)
+    for (int B = A; B < nb; ++B) tiles.push_back(make_int2(A, B));
+  GMGM_HIP(c, hipMemcpyAsync(wT, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  GMGM_HIP(c, hipStreamSynchronize(st));   // the host vector must outlive the copy
+  double* P = (double*)wP;
+  const int64_t np2 = (int64_t)n_split * pp * pp / 2;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(np2, 256)), dim3(256), 0, st, (double2*)P, np2);
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, (float4*)bad_count, (int64_t)1);
+  for (int64_t r0 = 0; r0 < n; r0 += rows_c) {
+    const int64_t rows = std::min<int64_t>(rows_c, n - r0);
+    hipLaunchKernelGGL(block_offsets_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, row_ptr, col,
+                       val, nnz, p, r0, rows, nb, off, bad_rows, bad_count, c->dev_status);
+    SparseArgs sa{row_ptr, col, val, off, r0, rows, (rows + n_split - 1) / n_split, (const int2*)wT, pp, P};
+    hipEvent_t ev = timing_start(c);
+    hipLaunchKernelGGL(gram_sparse_tile_kernel, dim3((unsigned)n_pairs, (unsigned)n_split), dim3(SP_THREADS), 0,
+                       st, sa);
+    timing_stop(c, ev);
+  }
+  hipLaunchKernelGGL(gram_rows_generic_kernel, dim3(256), dim3(256), 0, st, row_ptr, col, val, bad_rows,
+                     bad_count, pp, P);
+  const unsigned g32 = (unsigned)((p + 31) / 32);
+  hipLaunchKernelGGL(gram_finish_kernel, dim3(g32, g32), dim3(256), 0, st, P, n_split, pp, p, zs, cs, (double)n, G);
+  GMGM_HIP(c, hipGetLastError());
+  return GMGM_OK;
+}
+
 static gmgm_status gram_impl(gmgm_ctx* c, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
                              const int32_t* col, const float* val, const double* zs, const double* cs, float* G) {
   if (n < 1 || p < 1 || p > 65536 || nnz < 0)
@@ -223,6 +443,7 @@ static gmgm_status gram_impl(gmgm_ctx* c, int64_t n, int64_t p, int64_t nnz, con
                    (long long)n, (long long)p, (long long)nnz);
   if (!row_ptr || !G || (nnz > 0 && !col)) return set_err(c, GMGM_E_ARG, "null pointer argument");
   GMGM_HIP(c, hipSetDevice(c->device));
+  if (gram_use_sparse(n, p, nnz)) return gram_sparse(c, n, p, nnz, row_ptr, col, val, zs, cs, G);
   hipStream_t st = c->stream;
   const int64_t pp = (p + GT - 1) / GT * GT;
   const int nt = (int)(pp / GT);

@@ -37,9 +37,22 @@ def _dev(*arrs):
     return [None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
 
 
-def _gram_gpu(lib, rp, col, val, n, p):
+def _gram_gpu(lib, rp, col, val, n, p, path=None):
+    """path: None (the library's choice), "dense" (FP32 MFMA panels) or
+    "sparse" (products of the nonzeros into FP64 LDS tiles)."""
+    import os
     rpd, cd, vd = _dev(rp, col, val)
-    return lib.gram(rpd, cd, vd, n, p).cpu().numpy()
+    old = os.environ.get("GMGM_GRAM_PATH")
+    if path is not None:
+        os.environ["GMGM_GRAM_PATH"] = path
+    try:
+        return lib.gram(rpd, cd, vd, n, p).cpu().numpy()
+    finally:
+        if path is not None:
+            if old is None:
+                del os.environ["GMGM_GRAM_PATH"]
+            else:
+                os.environ["GMGM_GRAM_PATH"] = old
 
 
 def _check_gram(G, Gref, label):
@@ -51,13 +64,51 @@ def _check_gram(G, Gref, label):
     assert np.all(err <= tol), (label, float(np.max(err / tol)))
 
 
+@pytest.mark.parametrize("path", ["dense", "sparse"])
 @pytest.mark.parametrize("n,p,clusters,zipf,seed", [(2000, 500, 8, False, 1000), (3001, 700, 5, True, 7),
                                                     (257, 31, 3, False, 8)])
-def test_gram_parity_generator(lib, n, p, clusters, zipf, seed):
+def test_gram_parity_generator(lib, n, p, clusters, zipf, seed, path):
     X = _nb(n, p, clusters, zipf, seed)
     rp, col, val = synth.dense_to_csr(X)
-    G = _gram_gpu(lib, rp, col, val, n, p)
-    _check_gram(G, oracle.gram_csr(rp, col, val, n, p), f"{n}x{p}")
+    G = _gram_gpu(lib, rp, col, val, n, p, path)
+    _check_gram(G, oracle.gram_csr(rp, col, val, n, p), f"{n}x{p} {path}")
+
+
+def test_gram_sparse_path_unsorted_duplicate_and_block_edges(lib):
+    """Sparse path: rows whose columns are not strictly increasing (shuffled,
+    duplicated) mixed with sorted rows, columns on both sides of the 128-column
+    block edges, p not a multiple of 128, empty rows, 5%-dense rows."""
+    rng = np.random.default_rng(11)
+    n, p = 3000, 777
+    rows = []
+    for r in range(n):
+        m = int(rng.binomial(p, 0.05))
+        c = np.sort(rng.choice(p, m, replace=False))
+        if r % 7 == 0 and m > 1:
+            rng.shuffle(c)
+        if r % 11 == 0 and m > 0:
+            c = np.concatenate([c, c[:2]])
+        if r % 13 == 0:
+            c = np.array([127, 128, 255, 256, 767, 768, 776], dtype=np.int64)
+        if r % 17 == 0:
+            c = np.zeros(0, np.int64)
+        rows.append(c.astype(np.int32))
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([c.size for c in rows])
+    col = np.concatenate(rows)
+    val = rng.standard_normal(col.size).astype(np.float32)
+    X = np.zeros((n, p))
+    np.add.at(X, (np.repeat(np.arange(n), np.diff(rp)), col), val.astype(np.float64))
+    Gref = X.T @ X
+    for path in ("sparse", "dense"):
+        _check_gram(_gram_gpu(lib, rp, col, val, n, p, path), Gref, path)
+    _check_gram(_gram_gpu(lib, rp, col, None, n, p, "sparse"), _ones_gram(rp, col, n, p), "sparse binary")
+
+
+def _ones_gram(rp, col, n, p):
+    X = np.zeros((n, p))
+    np.add.at(X, (np.repeat(np.arange(n), np.diff(rp)), col), 1.0)
+    return X.T @ X
 
 
 def test_gram_parity_workload_100k_by_2000(lib):
@@ -68,13 +119,14 @@ def test_gram_parity_workload_100k_by_2000(lib):
     _check_gram(G, oracle.gram_dense(X), "100k x 2000")
 
 
-def test_gram_binary_values_duplicates_empty_rows_and_tiny(lib):
+@pytest.mark.parametrize("path", ["dense", "sparse"])
+def test_gram_binary_values_duplicates_empty_rows_and_tiny(lib, path):
     rng = np.random.default_rng(3)
     X = (rng.random((300, 45)) < 0.1).astype(np.float32)
     X[17] = 0
     X[299] = 0
     rp, col, _ = synth.dense_to_csr(X)
-    G = _gram_gpu(lib, rp, col, None, 300, 45)            # implicit ones
+    G = _gram_gpu(lib, rp, col, None, 300, 45, path)      # implicit ones
     _check_gram(G, oracle.gram_dense(X), "binary")
     # duplicate column entries add up (row 0 holds column 3 twice)
     rp2 = np.array([0, 3, 4], dtype=np.int64)
@@ -84,21 +136,24 @@ def test_gram_binary_values_duplicates_empty_rows_and_tiny(lib):
     Xd[0, 3] = 3.5
     Xd[0, 1] = -1.0
     Xd[1, 0] = 4.0
-    _check_gram(_gram_gpu(lib, rp2, col2, val2, 2, 5), oracle.gram_dense(Xd), "duplicates")
+    _check_gram(_gram_gpu(lib, rp2, col2, val2, 2, 5, path), oracle.gram_dense(Xd), "duplicates")
     # one cell, one gene; all-zero matrix
-    G1 = _gram_gpu(lib, np.array([0, 1], np.int64), np.array([0], np.int32), np.array([3.0], np.float32), 1, 1)
+    G1 = _gram_gpu(lib, np.array([0, 1], np.int64), np.array([0], np.int32), np.array([3.0], np.float32), 1, 1,
+                   path)
     assert G1[0, 0] == np.float32(9.0)
-    Gz = _gram_gpu(lib, np.zeros(11, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32), 10, 300)
+    Gz = _gram_gpu(lib, np.zeros(11, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32), 10, 300, path)
     assert not Gz.any()
 
 
-def test_gram_full_gene_width_sampled(lib):
-    """20k genes (79 x 79 output tiles, two densified panels): every diagonal
-    entry exact-checked, a 96 x 96 sample of entries against FP64."""
+@pytest.mark.parametrize("path", ["dense", "sparse"])
+def test_gram_full_gene_width_sampled(lib, path):
+    """20k genes (dense: 79 x 79 output tiles, two densified panels; sparse:
+    157 x 158 / 2 tile pairs): every diagonal entry exact-checked, a 96 x 96
+    sample of entries against FP64."""
     import scipy.sparse as sp
     n, p = 40_000, 20_000
     rp, col, val = synth.csr_proxy(n, p, 0.05, seed=3000, workers=4)
-    G = _gram_gpu(lib, rp, col, val, n, p)
+    G = _gram_gpu(lib, rp, col, val, n, p, path)
     assert np.array_equal(G, G.T)
     diag = np.bincount(col, weights=val.astype(np.float64) ** 2, minlength=p)
     assert np.all(np.abs(np.diag(G) - diag) <= 1e-5 * diag + 1e-30)
@@ -110,8 +165,9 @@ def test_gram_full_gene_width_sampled(lib):
     _check_gram(np.ascontiguousarray(G[np.ix_(idx, idx)]), Gref, "20k sample")
 
 
-def test_gram_errors(lib):
-    import torch
+@pytest.mark.parametrize("path", ["dense", "sparse"])
+def test_gram_errors(lib, path, monkeypatch):
+    monkeypatch.setenv("GMGM_GRAM_PATH", path)
     rp, col, val = _dev(np.array([0, 2, 1], np.int64), np.array([0, 1], np.int32), np.array([1, 2], np.float32))
     with pytest.raises(lib.GmgmError) as ei:                # row_ptr decreasing
         lib.gram(rp, col, val, 2, 3)
@@ -164,6 +220,11 @@ def test_eigh_parity_generator_grams(lib, n, p, clusters, zipf, seed):
     G32 = _sym32(oracle.gram_dense(X))
     w, V, rank = _eigh_gpu(lib, G32)
     _check_eigh(G32, w, V, rank, f"{p}")
+    (Gd,) = _dev(G32)                                        # eigenvalues only
+    w2, Vt2, rank2 = lib.eigh_small(Gd, vectors=False)
+    assert Vt2 is None and rank2 == rank
+    e_ref = oracle.eigh_desc(G32.astype(np.float64))[0]
+    assert np.all(np.abs(w2.cpu().numpy() - e_ref) <= 64 * p * 2.0 ** -52 * abs(e_ref[0]))
 
 
 def test_eigh_workload_2000_rank_deficient_and_tiny(lib):

