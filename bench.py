@@ -13,13 +13,14 @@ in HBM before timing starts.  Prints ONE JSON line on stdout; progress goes
 to stderr.
 
 The other steps of the path are timed once each at the same workload's shape
-(reported under "stages", not part of the metric): the gene-axis Gram of a
-1M x 20k 5%-dense CSR, its FP64 eigendecomposition, the cell-axis factor
-(r = 100), the eigenvalue MLE on the resulting spectra, and the shared-cell
-path with 1M x 50k binary peaks at 2% (transposes, subspace iteration for
-cells and peaks with k = 110, q = 2, the three-axis solve).  The CSR is the
-fast seeded stand-in (same shape, density and log1p value range as the NB
-generator, without its cluster structure).
+(reported under "stages", not part of the metric) on the 1M x 20k workload's
+own data: log1p(NB counts) at 5% nonzeros with 40 Zipf-sized clusters and a
+rank-8 cell factor, drawn on the GPU (synth.nb_log1p_csr_gpu).  Its gene-axis
+Gram (the library's path and both paths forced), FP64 eigendecomposition, the
+cell-axis factor (r = 100), the eigenvalue MLE on the resulting spectra, the
+recomposition on that factor and psi, and the shared-cell path with 1M x 50k
+binary peaks at 2% drawn from the same cell factor (transposes, subspace
+iteration for cells and peaks with k = 110, q = 2, the three-axis solve).
 
 --profile-run runs one step of the metric path and one 1 GiB device copy (the
 reference kernel for scaling HBM traffic counters) and prints nothing else.
@@ -88,10 +89,10 @@ def workload(n, r, seed=3000):
     return V, psi
 
 
-def cpu_baseline(V, psi, k, n_clusters=40, seed=3000, per_cluster=4, edge=32):
+def cpu_baseline(V, psi, k, n_clusters=40, seed=3000, per_cluster=8, edge=32):
     """The CPU oracle (unchanged) on a stratified sample of rows of the same
     workload: the first and last `edge` rows and `per_cluster` random rows of
-    every cluster (about 20 s of CPU work at this size)."""
+    every cluster (384 rows, about 30 s of CPU work at this size)."""
     import numpy as np
 
     import oracle
@@ -122,20 +123,24 @@ def cpu_baseline(V, psi, k, n_clusters=40, seed=3000, per_cluster=4, edge=32):
                       f"{n / (rows.size / dt) / 3600:.1f} h (extrapolated)"}
 
 
-def stages(g, n, p, r, workers, multimodal=True):
+def stages(g, n, p, r, multimodal=True):
     """Gram, eigendecomposition, cell factor and solve at the workload's shape."""
     import numpy as np
     import torch
 
     import synth
-    out = {"input": f"{n} x {p} CSR stand-in, 5% dense, seed 3000", "r": r}
+    out = {"input": f"{n} x {p} log1p(NB counts), 5% nonzeros, 40 Zipf-sized clusters, rank-8 cell "
+                    f"factor (the NB/log1p recipe drawn on the GPU, seed 3000)", "r": r}
     t0 = time.perf_counter()
-    rp, col, val = synth.csr_proxy(n, p, 0.05, seed=3000, workers=workers)
-    nnz = int(rp[-1])
+    labels = synth.cluster_labels(n, 40, True, 3000)
+    beta0 = synth._calibrate_beta0(0.05, p, 40, labels, 3000)
+    del labels
+    A = synth.cell_factor_gpu(n, 3000)
+    rpd, cd, vd = synth.nb_log1p_csr_gpu(n, p, 40, True, 3000, beta0=beta0, A=A)
+    nnz = int(rpd[-1])
     out["nnz"] = nnz
-    log(f"stages: generated {nnz} nonzeros in {time.perf_counter() - t0:.1f} s")
-    rpd, cd, vd = (torch.from_numpy(a).cuda() for a in (rp, col, val))
-    del rp, col, val
+    log(f"stages: generated {nnz} nonzeros ({nnz / (n * p):.4f} dense) in {time.perf_counter() - t0:.1f} s")
+    torch.cuda.empty_cache()
     G = torch.empty(p, p, dtype=torch.float32, device="cuda")
 
     def timed(fn, reps):
@@ -157,21 +162,34 @@ def stages(g, n, p, r, workers, multimodal=True):
 
     g.gram(rpd, cd, vd, n, p, out=G)                      # warm-up
     wall, kms, cnt, _ = timed(lambda: g.gram(rpd, cd, vd, n, p, out=G), 1)
-    pp = (p + 255) // 256 * 256
-    dense = float(n) * pp * pp                            # 2 n pp^2 / 2: upper tiles incl. diagonal tiles
-    row_nnz = np.diff(rpd.cpu().numpy()).astype(np.float64)
-    algo = float(np.sum(row_nnz * (row_nnz + 1.0)))      # 2 sum_c nnz_c (nnz_c + 1) / 2: the method's products
-    out["gram"] = {"ms": wall * 1e3, "tile_kernel_ms": kms, "launches": cnt, "bound": "mfma",
-                   "unit": "TFLOP/s", "achieved": algo / (kms * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp32"],
-                   "frac": algo / (kms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+    row_nnz = torch.diff(rpd).to(torch.float64)
+    algo = float(torch.sum(row_nnz * (row_nnz + 1.0)))   # 2 sum_c nnz_c (nnz_c + 1) / 2: the method's products
+    del row_nnz
+    out["gram"] = {"ms": wall * 1e3, "tile_kernel_ms": kms, "launches": cnt, "bound": "alu",
+                   "unit": "TFLOP/s", "achieved": algo / (wall * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp32"],
+                   "frac": algo / (wall * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
                    "algorithmic_flops": algo,
                    "flops_kind": "2 sum_c nnz_c (nnz_c + 1) / 2: products of each cell's nonzeros (upper half)",
-                   "executed_dense_flops": dense,
-                   "executed_tflops": dense / (kms * 1e-3) / 1e12,
-                   "executed_frac": dense / (kms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
-                   "executed_kind": "dense-panel FP32 MFMA, n * p_pad^2 (upper tiles)"}
-    log(f"stages: gram {wall * 1e3:.1f} ms ({out['gram']['achieved']:.2f} TF/s algorithmic, "
-        f"{out['gram']['executed_tflops']:.1f} TF/s executed)")
+                   "path": "the library's choice from the shape"}
+    # both paths forced, for the record of why the choice is made
+    pp = (p + 255) // 256 * 256
+    for path in ("dense", "sparse"):
+        os.environ["GMGM_GRAM_PATH"] = path
+        try:
+            g.gram(rpd, cd, vd, n, p, out=G)
+            w2, k2, c2, _ = timed(lambda: g.gram(rpd, cd, vd, n, p, out=G), 1)
+        finally:
+            del os.environ["GMGM_GRAM_PATH"]
+        rec = {"ms": w2 * 1e3, "tile_kernel_ms": k2, "algorithmic_tflops": algo / (w2 * 1e-3) / 1e12}
+        if path == "dense":
+            dense = float(n) * pp * pp                    # 2 n pp^2 / 2: upper tiles incl. diagonal tiles
+            rec.update(executed_flops=dense, executed_tflops=dense / (k2 * 1e-3) / 1e12,
+                       executed_kind="dense-panel FP32 MFMA, n * p_pad^2 (upper tiles)")
+        else:
+            rec.update(executed_kind="FP64 products of each row's nonzeros into 128 x 128 LDS tiles")
+        out["gram"][path] = rec
+    log(f"stages: gram {wall * 1e3:.1f} ms ({out['gram']['achieved']:.2f} TF/s algorithmic); forced paths: "
+        f"dense {out['gram']['dense']['ms']:.1f} ms, sparse {out['gram']['sparse']['ms']:.1f} ms")
     wall, kms, cnt, res = timed(lambda: g.eigh_small(G), 1)
     w, Vt, rank = res
     out["eigh"] = {"ms": wall * 1e3, "solver_ms": kms, "p": p, "rank": rank,
@@ -212,8 +230,8 @@ def stages(g, n, p, r, workers, multimodal=True):
     del sk, G
     torch.cuda.empty_cache()
     if multimodal:
-        out["shared_cells"] = shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, workers)
-    del rpd, cd, vd
+        out["shared_cells"] = shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, A)
+    del rpd, cd, vd, A
     torch.cuda.empty_cache()
     out["tensor_solve"] = tensor_solve(g)
     out["gene_axis_recompose"] = gene_axis_recompose(g)
@@ -297,7 +315,7 @@ def chain_recompose(g, U, psi, k, prec="bf16", steps=3):
     st = g.recompose_topk(U, psi, k, prec=prec, out=out, stats=True).stats
     flops = 2.0 * r * n * n
     log(f"stages: chain recompose {dt * 1e3:.1f} ms/step, sweep {sweep_ms:.1f} ms, stats {st}")
-    return {"input": "cell factor of the CSR stand-in (gmgm_sketch, r = %d) and its solved psi" % r,
+    return {"input": "cell factor of the NB/log1p matrix above (gmgm_sketch, r = %d) and its solved psi" % r,
             "rows_per_s": n / dt, "ms_per_step": dt * 1e3, "sweep_ms": sweep_ms,
             "sweep_frac_of_peak": flops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], "stats": st}
 
@@ -339,22 +357,23 @@ def gene_axis_recompose(g, n=20_000, k=10, seed=3000):
     return res
 
 
-def shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, workers, p_pk=50_000, k_over=10, q=2):
-    """Cells shared by RNA (the CSR above) and binary ATAC peaks (1M x 50k, 2%):
+def shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, A, p_pk=50_000, k_over=10, q=2):
+    """Cells shared by RNA (the CSR above) and binary ATAC peaks (1M x 50k, 2%,
+    Bernoulli(sigmoid) of the RNA's rank-8 cell factor A plus noise):
     subspace iteration for cells on [X_rna | X_pk] and for peaks on X_pk^T, then
     the three-axis solve."""
-    import numpy as np
     import torch
 
     import synth
     t0 = time.perf_counter()
-    prp, pcol, _ = synth.csr_proxy(n, p_pk, 0.02, seed=4000, workers=workers)
+    prp, pcol = synth.peaks_csr_gpu(A, p_pk, 0.02, seed=4000)
     log(f"stages: peaks generated, {int(prp[-1])} nonzeros in {time.perf_counter() - t0:.1f} s")
     rna = g.CsrMatrix(rpd, cd, vd, n, p)
-    pk = g.CsrMatrix(torch.from_numpy(prp).cuda(), torch.from_numpy(pcol).cuda(), None, n, p_pk)
+    pk = g.CsrMatrix(prp, pcol, None, n, p_pk)
     del prp, pcol
-    res = {"input": f"RNA {n} x {p} ({nnz} nonzeros) + binary peaks {n} x {p_pk} at 2% "
-                    f"({pk.nnz} nonzeros), seeds 3000 / 4000", "k": r + k_over, "q": q}
+    torch.cuda.empty_cache()
+    res = {"input": f"RNA {n} x {p} ({nnz} nonzeros) + binary peaks {n} x {p_pk} at 2% from the RNA's "
+                    f"cell factor ({pk.nnz} nonzeros), seeds 3000 / 4000", "k": r + k_over, "q": q}
     torch.cuda.synchronize()
     t = time.perf_counter()
     rna_t, pk_t = rna.transpose(), pk.transpose()
@@ -578,7 +597,7 @@ def main():
     if not args.no_stages:
         del out_main, ref
         torch.cuda.empty_cache()
-        result["stages"] = stages(g, n, 20_000, r, workers=min(16, os.cpu_count() or 1),
+        result["stages"] = stages(g, n, 20_000, r,
                                   multimodal=not args.no_multimodal)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on sampled rows)")

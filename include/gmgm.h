@@ -249,11 +249,21 @@ gmgm_status gmgm_significance_threshold(gmgm_ctx_t ctx, int64_t d_l, int32_t n_m
  *   col         nnz int32 column indices in [0, p) (device).  Duplicates add up.
  *   val         nnz FP32 values (device), or NULL for all ones (binary data).
  *   G           p x p FP32 output, row-major (device); exactly symmetric.
- * FP32 products accumulate in FP32 over at most 2048 rows, then in FP64.
- * Workspace: a dense panel of X rows (<= 2 GiB) and FP64 partial sums
- * (p_pad^2 x splits, <= 8 GiB, p_pad = p rounded up to 256).  Malformed CSR is
- * reported as GMGM_E_SHAPE and non-finite values as GMGM_E_DOMAIN by the next
- * synchronising call; asynchronous otherwise.
+ * Two paths, picked from (n, p, nnz) without synchronising (the environment
+ * variable GMGM_GRAM_PATH=dense or =sparse forces one):
+ *   sparse  the products of each row's nonzeros, added in FP64 into 128 x 128
+ *           tiles (the input-sparsity appendix: X is never densified).  The
+ *           nonzeros are first copied block-major (nnz x 5 bytes); rows whose
+ *           columns are not strictly increasing take a slower exact route.
+ *           Workspace: the copy, per-row block offsets (<= 2 GiB per row
+ *           chunk) and FP64 partials (p_pad^2 x splits, p_pad = p rounded up
+ *           to 128).  Result order-dependent in the last FP64 bits only.
+ *   dense   row panels densified (<= 2 GiB), FP32 MFMA products accumulated
+ *           in FP32 over at most 2048 rows, then in FP64; partials p_pad^2 x
+ *           splits (<= 8 GiB, p_pad = p rounded up to 256).  Deterministic
+ *           for CSR input without duplicate columns.
+ * Malformed CSR is reported as GMGM_E_SHAPE and non-finite values as
+ * GMGM_E_DOMAIN by the next synchronising call; asynchronous otherwise.
  */
 gmgm_status gmgm_gram(gmgm_ctx_t ctx, int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
                       const int32_t* col, const float* val, float* G);

@@ -4,7 +4,9 @@
 // formed only for the small axis; the large axis is reached through its
 // singular vectors, Algorithm 1's first loop).  No centring or scaling.
 //
-// Design: row panels of X are densified into HBM (zero-padded to a multiple
+// Two paths (picked from the shape, see gram_use_sparse): a sparse one that
+// multiplies only each row's nonzeros (further below), and dense panels:
+// row panels of X are densified into HBM (zero-padded to a multiple
 // of 256 genes), then a symmetric rank-k update runs on the FP32 MFMA
 // (32x32x2): one 256 x 256 output tile per workgroup of 16 waves (64 x 64
 // each), only tiles with J >= I,
@@ -214,16 +216,20 @@ __global__ void __launch_bounds__(256) gram_finish_kernel(const double* __restri
 // x_ra x_rb of its entries with a <= b are added into 128 x 128 FP64 tiles
 // held in LDS (one workgroup per tile pair (A, B), A <= B, and row split).
 // Work is sum_r nnz_r^2 / 2 products instead of n p^2 / 2 for dense panels.
-// The entries of row r in column block q are [off[q][r], off[q + 1][r])
-// relative to row_ptr[r], which needs strictly increasing columns per row;
-// other rows (unsorted or duplicate columns) take all ordered pairs with
-// global FP64 atomics.
+// The nonzeros are first copied block-major: the entries of column block q
+// for all rows, row after row (a one-byte column within the block and the
+// value), so that a tile pair reads two contiguous streams.  Finding each
+// row's block boundaries needs strictly increasing columns per row; other
+// rows (unsorted or duplicate columns) take every ordered pair with global
+// FP64 atomics.
 constexpr int ST = 128;               // sparse tile edge (FP64 tile: 128 KB of LDS)
 constexpr int SP_THREADS = 1024;
+constexpr int SCAN_T = 1024;          // rows per scan chunk
 
-// One wave per row of [r0, r0 + rows): block offsets of sorted rows (local
-// row index), zero offsets (no work) for every other row; unsorted rows are
-// listed for the generic kernel, malformed rows reported and skipped.
+// One wave per row of [r0, r0 + rows): block offsets within the row,
+// off[q][i] = number of the row's entries with column < q * ST (q = 0..nb),
+// for sorted rows; zero offsets (no work) for every other row.  Unsorted rows
+// are listed for the generic kernel, malformed rows reported and skipped.
 __global__ void __launch_bounds__(256) block_offsets_kernel(const int64_t* __restrict__ rp,
                                                             const int32_t* __restrict__ col,
                                                             const float* __restrict__ val, int64_t nnz,
@@ -270,16 +276,135 @@ __global__ void __launch_bounds__(256) block_offsets_kernel(const int64_t* __res
   for (int q = last + 1 + lane; q <= nb; q += 64) off[(size_t)q * rows + i] = (int)(e - b);
 }
 
+// Exclusive scan of SCAN_T values per workgroup (16 waves); returns the
+// thread's exclusive prefix and leaves the workgroup total in *total.
+__device__ inline unsigned block_exclusive_scan(unsigned v, unsigned* wsum, unsigned* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const unsigned s = lane < 16 ? wsum[lane] : 0u;
+    unsigned inc = s;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const unsigned y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
+    }
+    if (lane < 16) wsum[16 + lane] = inc - s;
+    if (lane == 15) wsum[32] = inc;
+  }
+  __syncthreads();
+  const unsigned r = x - v + wsum[16 + w];
+  *total = wsum[32];
+  __syncthreads();
+  return r;
+}
+
+// Segment starts per (block q, row r) relative to the block's region, within
+// a chunk of SCAN_T rows: S[q][r] (row stride rows + 1); chunk sums into
+// tot[q][chunk].  Grid (chunks, nb).
+__global__ void __launch_bounds__(SCAN_T) seg_scan_kernel(const int* __restrict__ off, int64_t rows,
+                                                          int nchunks, unsigned* __restrict__ S,
+                                                          unsigned* __restrict__ tot) {
+  __shared__ unsigned wsum[33];
+  const int q = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * SCAN_T + threadIdx.x;
+  const unsigned c = r < rows ? (unsigned)(off[(size_t)(q + 1) * rows + r] - off[(size_t)q * rows + r]) : 0u;
+  unsigned total;
+  const unsigned ex = block_exclusive_scan(c, wsum, &total);
+  if (r < rows) S[(size_t)q * (rows + 1) + r] = ex;
+  if (threadIdx.x == 0) tot[(size_t)q * nchunks + blockIdx.x] = total;
+}
+
+// Per block q (one workgroup each): the chunk sums scanned in place into
+// chunk bases; T[q] = the block's entry count.
+__global__ void __launch_bounds__(SCAN_T) chunk_base_kernel(unsigned* __restrict__ tot, int nchunks,
+                                                            unsigned long long* __restrict__ T) {
+  __shared__ unsigned wsum[33];
+  const int q = blockIdx.x;
+  unsigned carry = 0;
+  for (int c0 = 0; c0 < nchunks; c0 += SCAN_T) {
+    const int c = c0 + (int)threadIdx.x;
+    const unsigned v = c < nchunks ? tot[(size_t)q * nchunks + c] : 0u;
+    unsigned total;
+    const unsigned ex = block_exclusive_scan(v, wsum, &total);
+    if (c < nchunks) tot[(size_t)q * nchunks + c] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) T[q] = carry;
+}
+
+// Region starts R0[q] = sum of T over blocks before q (one thread; nb <= 512),
+// and the end sentinel S[q][rows] = T[q].
+__global__ void region_kernel(const unsigned long long* __restrict__ T, int nb, int64_t rows,
+                              unsigned long long* __restrict__ R0, unsigned* __restrict__ S) {
+  if (threadIdx.x == 0) {
+    unsigned long long acc = 0;
+    for (int q = 0; q < nb; ++q) {
+      R0[q] = acc;
+      acc += T[q];
+    }
+  }
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) S[(size_t)q * (rows + 1) + rows] = (unsigned)T[q];
+}
+
+// S[q][r] += the base of r's chunk (absolute within the block's region).
+__global__ void seg_add_kernel(unsigned* __restrict__ S, const unsigned* __restrict__ tot, int64_t rows, int nb,
+                               int nchunks) {
+  const int64_t total = (int64_t)nb * rows;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(x / rows);
+    const int64_t r = x - (int64_t)q * rows;
+    S[(size_t)q * (rows + 1) + r] += tot[(size_t)q * nchunks + r / SCAN_T];
+  }
+}
+
+// The block-major copy: one wave per row; entry t of a sorted row goes to
+// R0[q] + S[q][r] + (its rank within the row's block-q segment).  Rows whose
+// segments are empty (unsorted, malformed) copy nothing.
+__global__ void __launch_bounds__(256) block_scatter_kernel(const int64_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ col,
+                                                            const float* __restrict__ val, int64_t nnz,
+                                                            int64_t p, int64_t r0, int64_t rows,
+                                                            const int* __restrict__ off,
+                                                            const unsigned* __restrict__ S,
+                                                            const unsigned long long* __restrict__ R0,
+                                                            uint8_t* __restrict__ bcol, float* __restrict__ bval) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= rows) return;
+  const int64_t b = rp[r0 + i], e = rp[r0 + i + 1];
+  if (b < 0 || e < b || e > nnz) return;
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int c = col[t];
+    if (c < 0 || c >= p) continue;
+    const int q = c / ST;
+    const unsigned s0 = S[(size_t)q * (rows + 1) + i], s1 = S[(size_t)q * (rows + 1) + i + 1];
+    const int64_t rel = (t - b) - off[(size_t)q * rows + i];
+    if (rel < 0 || rel >= (int64_t)(s1 - s0)) continue;
+    const unsigned long long d = R0[q] + s0 + (unsigned long long)rel;
+    bcol[d] = (uint8_t)(c - q * ST);
+    bval[d] = val ? val[t] : 1.0f;
+  }
+}
+
 struct SparseArgs {
-  const int64_t* rp;   // row_ptr of X (global rows)
-  const int32_t* col;
-  const float* val;    // nullptr: all ones
-  const int* off;      // (nb + 1) x rows block offsets of this row chunk
-  int64_t r0, rows;    // the chunk: global rows [r0, r0 + rows)
-  int64_t rows_split;  // rows per split
-  const int2* tiles;   // (A, B), B >= A
-  int64_t pp;          // nb * ST
-  double* P;           // n_split x pp x pp FP64 partials (added to)
+  const unsigned* S;              // nb x (rows + 1) segment starts (relative to each block's region)
+  const unsigned long long* R0;   // region start of each block
+  const uint8_t* bcol;            // block-major copy: column within the block
+  const float* bval;              //                   value
+  int64_t rows;                   // rows of this chunk
+  int64_t rows_split;             // rows per split
+  const int2* tiles;              // (A, B), B >= A
+  int64_t pp;                     // nb * ST
+  double* P;                      // n_split x pp x pp FP64 partials (added to)
 };
 
 __global__ void __launch_bounds__(SP_THREADS) gram_sparse_tile_kernel(SparseArgs a) {
@@ -292,41 +417,39 @@ __global__ void __launch_bounds__(SP_THREADS) gram_sparse_tile_kernel(SparseArgs
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.y * a.rows_split;
   const int64_t hi = lo + a.rows_split < a.rows ? lo + a.rows_split : a.rows;
-  const int* offA0 = a.off + (size_t)A * a.rows;
-  const int* offA1 = offA0 + a.rows;
-  const int* offB0 = a.off + (size_t)B * a.rows;
-  const int* offB1 = offB0 + a.rows;
-  const int cA = A * ST, cB = B * ST;
+  const unsigned* SA = a.S + (size_t)A * (a.rows + 1);
+  const unsigned* SB = a.S + (size_t)B * (a.rows + 1);
+  const uint8_t* colA = a.bcol + a.R0[A];
+  const float* valA = a.bval + a.R0[A];
+  const uint8_t* colB = a.bcol + a.R0[B];
+  const float* valB = a.bval + a.R0[B];
   for (int64_t r = lo + tid; r < hi; r += SP_THREADS) {
-    const int a0 = offA0[r], a1 = offA1[r], b0 = offB0[r], b1 = offB1[r];
+    const unsigned a0 = SA[r], a1 = SA[r + 1], b0 = SB[r], b1 = SB[r + 1];
     if (a0 >= a1 || b0 >= b1) continue;
-    const int64_t base = a.rp[a.r0 + r];
-    const int32_t* cr = a.col + base;
-    const float* vr = a.val ? a.val + base : nullptr;
     // eight B entries in registers at a time, every A entry against them
-    for (int j0 = b0; j0 < b1; j0 += 8) {
+    for (unsigned j0 = b0; j0 < b1; j0 += 8) {
       int cb[8];
       double vb[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int j = j0 + u < b1 ? j0 + u : b1 - 1;
-        cb[u] = cr[j] - cB;
-        vb[u] = vr ? (double)vr[j] : 1.0;
+        const unsigned j = j0 + u < b1 ? j0 + u : b1 - 1;
+        cb[u] = colB[j];
+        vb[u] = (double)valB[j];
       }
-      const int iend = diag ? (a1 < j0 + 8 ? a1 : j0 + 8) : a1;   // diagonal tile: i <= j
-      for (int i = a0; i < iend; ++i) {
-        const double va = vr ? (double)vr[i] : 1.0;
-        double* trow = t + (cr[i] - cA) * ST;
+      const unsigned iend = diag ? (a1 < j0 + 8 ? a1 : j0 + 8) : a1;   // diagonal tile: i <= j
+      for (unsigned i = a0; i < iend; ++i) {
+        const double va = (double)valA[i];
+        double* trow = t + (int)colA[i] * ST;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const int j = j0 + u;
+          const unsigned j = j0 + u;
           if (j < b1 && (!diag || j >= i)) atomicAdd(trow + cb[u], va * vb[u]);
         }
       }
     }
   }
   __syncthreads();
-  double* Pt = a.P + (size_t)blockIdx.y * a.pp * a.pp + (size_t)cA * a.pp + cB;
+  double* Pt = a.P + (size_t)blockIdx.y * a.pp * a.pp + (size_t)A * ST * a.pp + (size_t)B * ST;
   for (int q = tid; q < ST * ST; q += SP_THREADS) {
     const int x = q / ST, y = q % ST;
     if (t[q] != 0.0) Pt[(size_t)x * a.pp + y] += t[q];
@@ -393,21 +516,35 @@ static gmgm_status gram_sparse(gmgm_ctx* c, int64_t n, int64_t p, int64_t nnz, c
   const int nb = (int)((p + ST - 1) / ST);
   const int64_t pp = (int64_t)nb * ST;
   const int n_pairs = nb * (nb + 1) / 2;
-  // row chunks: block offsets of at most 1 GiB
-  const int64_t rows_c = std::min<int64_t>(n, std::max<int64_t>(4096, ((int64_t)1 << 30) / (4 * (nb + 1))));
+  // row chunks: offsets and segment starts of at most 2 GiB together
+  const int64_t rows_c = std::min<int64_t>(n, std::max<int64_t>(SCAN_T, ((int64_t)1 << 31) / (8 * (nb + 1))));
+  const int nchunks = (int)((rows_c + SCAN_T - 1) / SCAN_T);
   // row splits: enough workgroups to cover the chip, >= 4096 rows each, partials <= 8 GiB
   int n_split = (int)std::min<int64_t>(64, (2048 + n_pairs - 1) / n_pairs);
   n_split = (int)std::max<int64_t>(1, std::min<int64_t>(n_split, rows_c / 4096));
   while (n_split > 1 && (double)n_split * pp * pp * 8 > 8.0 * (1 << 30)) n_split--;
 
-  void *wO, *wP, *wT;
-  const size_t off_bytes = ((size_t)(nb + 1) * rows_c * 4 + 255) & ~(size_t)255;
-  GMGM_TRY(ws_get(c, WS_GRAM0, 256 + off_bytes + (size_t)n * 4, &wO));
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_off = up((size_t)(nb + 1) * rows_c * 4);
+  const size_t b_S = up((size_t)nb * (rows_c + 1) * 4);
+  const size_t b_tot = up((size_t)nb * nchunks * 4);
+  const size_t b_T = up((size_t)nb * 8);
+  const size_t b_bad = up((size_t)n * 4);
+  void *wO, *wP, *wT, *wB;
+  GMGM_TRY(ws_get(c, WS_GRAM0, 256 + b_off + b_S + b_tot + 2 * b_T + b_bad, &wO));
   GMGM_TRY(ws_get(c, WS_GRAM1, (size_t)n_split * pp * pp * sizeof(double), &wP));
   GMGM_TRY(ws_get(c, WS_GRAM2, (size_t)n_pairs * sizeof(int2), &wT));
-  int* bad_count = (int*)wO;
-  int* off = (int*)((char*)wO + 256);
-  int* bad_rows = (int*)((char*)wO + 256 + off_bytes);
+  GMGM_TRY(ws_get(c, WS_GRAM3, up((size_t)std::max<int64_t>(nnz, 1) * 4) + up((size_t)std::max<int64_t>(nnz, 1)), &wB));
+  char* w = (char*)wO;
+  int* bad_count = (int*)w;
+  int* off = (int*)(w + 256);
+  unsigned* S = (unsigned*)(w + 256 + b_off);
+  unsigned* tot = (unsigned*)(w + 256 + b_off + b_S);
+  unsigned long long* T = (unsigned long long*)(w + 256 + b_off + b_S + b_tot);
+  unsigned long long* R0 = (unsigned long long*)(w + 256 + b_off + b_S + b_tot + b_T);
+  int* bad_rows = (int*)(w + 256 + b_off + b_S + b_tot + 2 * b_T);
+  float* bval = (float*)wB;
+  uint8_t* bcol = (uint8_t*)wB + up((size_t)std::max<int64_t>(nnz, 1) * 4);
   std::vector<int2> tiles;
   tiles.reserve(n_pairs);
   for (int A = 0; A < nb; ++A)
@@ -420,9 +557,18 @@ static gmgm_status gram_sparse(gmgm_ctx* c, int64_t n, int64_t p, int64_t nnz, c
   hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, (float4*)bad_count, (int64_t)1);
   for (int64_t r0 = 0; r0 < n; r0 += rows_c) {
     const int64_t rows = std::min<int64_t>(rows_c, n - r0);
+    const int nch = (int)((rows + SCAN_T - 1) / SCAN_T);
     hipLaunchKernelGGL(block_offsets_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, row_ptr, col,
                        val, nnz, p, r0, rows, nb, off, bad_rows, bad_count, c->dev_status);
-    SparseArgs sa{row_ptr, col, val, off, r0, rows, (rows + n_split - 1) / n_split, (const int2*)wT, pp, P};
+    hipLaunchKernelGGL(seg_scan_kernel, dim3((unsigned)nch, (unsigned)nb), dim3(SCAN_T), 0, st, off, rows, nch, S,
+                       tot);
+    hipLaunchKernelGGL(chunk_base_kernel, dim3((unsigned)nb), dim3(SCAN_T), 0, st, tot, nch, T);
+    hipLaunchKernelGGL(region_kernel, dim3(1), dim3(256), 0, st, T, nb, rows, R0, S);
+    hipLaunchKernelGGL(seg_add_kernel, dim3(grid_for((int64_t)nb * rows, 256)), dim3(256), 0, st, S, tot, rows, nb,
+                       nch);
+    hipLaunchKernelGGL(block_scatter_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, row_ptr, col, val,
+                       nnz, p, r0, rows, off, S, R0, bcol, bval);
+    SparseArgs sa{S, R0, bcol, bval, rows, (rows + n_split - 1) / n_split, (const int2*)wT, pp, P};
     hipEvent_t ev = timing_start(c);
     hipLaunchKernelGGL(gram_sparse_tile_kernel, dim3((unsigned)n_pairs, (unsigned)n_split), dim3(SP_THREADS), 0,
                        st, sa);

@@ -24,6 +24,14 @@ Recipes (all seeded, all reproducible block by block):
   seeded Philox generator (normals, gamma, Poisson), for the many mid-sized
   instances of the warm-start training set; not used by any oracle
   comparison.
+* ``nb_log1p_csr_gpu`` -- the same recipe at full scale (1M x 20k at 5%):
+  row blocks drawn on the GPU, each block's own Philox stream, kept as CSR
+  (columns ascending); the rank-8 cell factor A can be passed in so that a
+  second modality shares it.
+* ``peaks_csr_gpu`` -- binary peaks of a modality sharing the cell axis:
+  Bernoulli(sigmoid(c0 + (A Bp^T)_ij / sqrt(8) + N(0, 1) noise)) with the
+  cells' rank-8 factor A, Bp ~ N(0, 1) per peak and c0 set for the requested
+  density, as CSR on the GPU.
 * ``rotating_objects`` -- tensors shaped like the paper's COIL-20 videos:
   objects of (frames x h x w) whose pixels vary with the frame angle through
   the first three circular harmonics (a rank-3 image per harmonic) plus noise.
@@ -49,6 +57,9 @@ __all__ = [
     "workload",
     "rotating_objects",
     "nb_log1p_gpu",
+    "nb_log1p_csr_gpu",
+    "peaks_csr_gpu",
+    "cell_factor_gpu",
     "ROW_BLOCK",
 ]
 
@@ -312,3 +323,86 @@ def nb_log1p_gpu(n, p, n_clusters, zipf, seed, beta0=0.0, device="cuda"):
     counts = torch.poisson(lam, generator=gen)
     del lam
     return torch.log1p(counts).to(torch.float32)
+
+
+def cell_factor_gpu(n, seed, device="cuda"):
+    """The rank-8 cell factor A (n x 8, FP64, N(0, 1)) of the full-scale
+    generators, from its own Philox stream."""
+    import torch
+    gen = torch.Generator(device=device).manual_seed(int(seed) * 7919 + 1)
+    return torch.randn(n, FACTOR_RANK, generator=gen, device=device, dtype=torch.float64)
+
+
+def nb_log1p_csr_gpu(n, p, n_clusters, zipf, seed, beta0=0.0, A=None, block=32768, device="cuda"):
+    """(row_ptr int64, col int32, val float32) device tensors of X = log1p(NB
+    counts), the ``nb_log1p`` recipe: gene parameters B, M, g from one Philox
+    stream, then row blocks of `block` rows each from its own stream (seed,
+    block).  A: the cell factor (n x 8 FP64 on `device`), default
+    cell_factor_gpu(n, seed)."""
+    import torch
+    gen = torch.Generator(device=device).manual_seed(int(seed))
+    f64 = torch.float64
+    B = torch.randn(p, FACTOR_RANK, generator=gen, device=device, dtype=f64)
+    M = torch.randn(n_clusters, p, generator=gen, device=device, dtype=f64)
+    g = torch.randn(p, generator=gen, device=device, dtype=f64) * math.sqrt(0.5)
+    lab = torch.from_numpy(cluster_labels(n, n_clusters, zipf, seed).astype(np.int64)).to(device)
+    if A is None:
+        A = cell_factor_gpu(n, seed, device)
+    counts, cols, vals = [], [], []
+    for b in range((n + block - 1) // block):
+        lo, hi = b * block, min(n, (b + 1) * block)
+        gb = torch.Generator(device=device).manual_seed(int(seed) * 1_000_003 + 7 + b)
+        mu = torch.exp(beta0 + 0.5 * (A[lo:hi] @ B.T) / math.sqrt(FACTOR_RANK) + M[lab[lo:hi]] + g[None, :])
+        lam = torch._standard_gamma(torch.full_like(mu, 1.0 / ALPHA), generator=gb)
+        lam *= ALPHA * mu
+        del mu
+        X = torch.log1p(torch.poisson(lam, generator=gb)).to(torch.float32)
+        del lam
+        nz = X != 0
+        counts.append(nz.sum(dim=1))
+        cols.append(nz.nonzero()[:, 1].to(torch.int32))
+        vals.append(X[nz])
+        del X, nz
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    torch.cumsum(torch.cat(counts), dim=0, out=row_ptr[1:])
+    return row_ptr, torch.cat(cols), torch.cat(vals)
+
+
+def peaks_csr_gpu(A, p, density, seed, block=16384, device="cuda"):
+    """(row_ptr int64, col int32) device tensors of a binary cells x peaks
+    matrix: entry (i, j) is 1 with probability sigmoid(c0 + (A Bp^T)_ij / sqrt(8)
+    + e_ij), e_ij ~ N(0, 1), Bp ~ N(0, 1) per peak; c0 by bisection so that
+    the mean probability over a 1M-entry sample equals `density`."""
+    import torch
+    n = A.shape[0]
+    gen = torch.Generator(device=device).manual_seed(int(seed))
+    Bp = torch.randn(p, FACTOR_RANK, generator=gen, device=device, dtype=torch.float64)
+    ii = torch.randint(0, n, (1_000_000,), generator=gen, device=device)
+    jj = torch.randint(0, p, (1_000_000,), generator=gen, device=device)
+    base = (A[ii] * Bp[jj]).sum(dim=1) / math.sqrt(FACTOR_RANK) + torch.randn(1_000_000, generator=gen,
+                                                                              device=device, dtype=torch.float64)
+    lo, hi = -30.0, 10.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if float(torch.sigmoid(mid + base).mean()) < density:
+            lo = mid
+        else:
+            hi = mid
+    c0 = 0.5 * (lo + hi)
+    Bp32 = (Bp / math.sqrt(FACTOR_RANK)).to(torch.float32)
+    counts, cols = [], []
+    for b in range((n + block - 1) // block):
+        r0, r1 = b * block, min(n, (b + 1) * block)
+        gb = torch.Generator(device=device).manual_seed(int(seed) * 1_000_003 + 11 + b)
+        z = A[r0:r1].to(torch.float32) @ Bp32.T
+        z += c0
+        z += torch.randn(z.shape, generator=gb, device=device, dtype=torch.float32)
+        hit = torch.rand(z.shape, generator=gb, device=device, dtype=torch.float32) < torch.sigmoid(z)
+        del z
+        counts.append(hit.sum(dim=1))
+        cols.append(hit.nonzero()[:, 1].to(torch.int32))
+        del hit
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    torch.cumsum(torch.cat(counts), dim=0, out=row_ptr[1:])
+    return row_ptr, torch.cat(cols)
+
