@@ -166,8 +166,8 @@ def stages(g, n, p, r, multimodal=True):
     algo = float(torch.sum(row_nnz * (row_nnz + 1.0)))   # 2 sum_c nnz_c (nnz_c + 1) / 2: the method's products
     del row_nnz
     out["gram"] = {"ms": wall * 1e3, "tile_kernel_ms": kms, "launches": cnt, "bound": "alu",
-                   "unit": "TFLOP/s", "achieved": algo / (wall * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp32"],
-                   "frac": algo / (wall * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+                   "unit": "TFLOP/s", "achieved": algo / wall / 1e12, "peak": PEAK_TFLOPS["fp32"],
+                   "frac": algo / wall / 1e12 / PEAK_TFLOPS["fp32"],
                    "algorithmic_flops": algo,
                    "flops_kind": "2 sum_c nnz_c (nnz_c + 1) / 2: products of each cell's nonzeros (upper half)",
                    "path": "the library's choice from the shape"}
@@ -180,7 +180,7 @@ def stages(g, n, p, r, multimodal=True):
             w2, k2, c2, _ = timed(lambda: g.gram(rpd, cd, vd, n, p, out=G), 1)
         finally:
             del os.environ["GMGM_GRAM_PATH"]
-        rec = {"ms": w2 * 1e3, "tile_kernel_ms": k2, "algorithmic_tflops": algo / (w2 * 1e-3) / 1e12}
+        rec = {"ms": w2 * 1e3, "tile_kernel_ms": k2, "algorithmic_tflops": algo / w2 / 1e12}
         if path == "dense":
             dense = float(n) * pp * pp                    # 2 n pp^2 / 2: upper tiles incl. diagonal tiles
             rec.update(executed_flops=dense, executed_tflops=dense / (k2 * 1e-3) / 1e12,
