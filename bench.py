@@ -36,6 +36,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "top-k precision rows/s at 1M cells, BF16-MFMA vs FP32, recall ≥0.999"
+WORKLOAD_TEXT = {
+    "chain": "cell-axis recomposition + top-k of the 1M cells x 20k genes workload (n=1,000,000, r=100, "
+             "k=10): the cell factor U = X V diag(e)^-1/2 and psi from the eigenvalue MLE, both computed by "
+             "the path from log1p(NB counts) at 5% nonzeros with 40 Zipf-sized clusters (generated, seed 3000)",
+    "proxy": "cell-axis recomposition + top-k at the 1M cells x 20k genes workload's shape (n=1,000,000, "
+             "r=100, k=10) on a stand-in cell factor (orthonormal, 40 Zipf clusters) and psi = 1/E of a "
+             "Marchenko-Pastur + spike spectrum",
+}
 PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
 # HBM traffic of the BF16 sweep kernel at this workload comes from the committed
 # rocprofv3 FETCH_SIZE / WRITE_SIZE summary, which records the SHA-256 of the
@@ -54,7 +62,7 @@ def sweep_sources_sha256():
     return h.hexdigest()
 
 
-def profiled_sweep_traffic(prec, n, r, k):
+def profiled_sweep_traffic(prec, n, r, k, workload_name):
     """(bytes per launch, note) of the BF16 sweep from the counter summary."""
     if (prec, n, r, k) != ("bf16", 1_000_000, 100, 10) or not os.path.exists(TRAFFIC_PROFILE):
         return None, "no counter profile for this configuration"
@@ -65,6 +73,10 @@ def profiled_sweep_traffic(prec, n, r, k):
                 vals["bytes"] = float(line.split(":", 1)[1])
             elif line.startswith("sweep_sources_sha256:"):
                 vals["sha"] = line.split(":", 1)[1].strip()
+            elif line.startswith("sweep_workload:"):
+                vals["workload"] = line.split(":", 1)[1].strip()
+    if vals.get("workload") != workload_name:
+        return None, "the counters were taken on another input"
     if "bytes" not in vals or vals.get("sha") != sweep_sources_sha256():
         return None, "the sweep's sources changed since the counters were taken"
     return vals["bytes"], os.path.relpath(TRAFFIC_PROFILE, ROOT)
@@ -78,8 +90,8 @@ def workload(n, r, seed=3000):
     """Stand-ins for the cell factor of the 1M x 20k, 5%-dense, 40-cluster
     workload (synth.cell_factor_proxy: orthonormal columns spanning 40 Zipf
     cluster centroids, the rank-8 factor and per-cell noise) and its psi (1/E of
-    a Marchenko-Pastur + spike spectrum of a 20k-gene Gram).  The chain's own
-    factor and solved psi are timed in stages["chain_recompose"]."""
+    a Marchenko-Pastur + spike spectrum of a 20k-gene Gram): a fixed input of
+    the same shape, timed beside the path's own factor."""
     import numpy as np
 
     import synth
@@ -87,6 +99,35 @@ def workload(n, r, seed=3000):
     E = synth.spectrum_proxy(20_000, n, 48, seed=seed)
     psi = np.ascontiguousarray(1.0 / E[:r])
     return V, psi
+
+
+def chain_inputs(g, n, p, r, seed=3000, log_steps=True):
+    """The 1M x 20k workload through the path up to the recomposition's inputs:
+    log1p(NB counts) at 5% nonzeros with 40 Zipf-sized clusters and a rank-8
+    cell factor drawn on the GPU, the gene Gram, its FP64 eigenpairs, the cell
+    factor U (r columns) and psi from the eigenvalue MLE of the two spectra."""
+    import torch
+
+    import synth
+    t0 = time.perf_counter()
+    labels = synth.cluster_labels(n, 40, True, seed)
+    beta0 = synth._calibrate_beta0(0.05, p, 40, labels, seed)
+    A = synth.cell_factor_gpu(n, seed)
+    rpd, cd, vd = synth.nb_log1p_csr_gpu(n, p, 40, True, seed, beta0=beta0, A=A)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    t = time.perf_counter()
+    G = g.gram(rpd, cd, vd, n, p)
+    w, Vt, rank = g.eigh_small(G)
+    U = g.sketch(rpd, cd, vd, n, p, Vt, w, r)
+    sol = g.solve_eigs([w[:r].contiguous(), w[:rank].contiguous()], [(0, 1)])
+    torch.cuda.synchronize()
+    nnz = int(rpd[-1])
+    if log_steps:
+        log(f"chain inputs: {nnz} nonzeros ({nnz / (n * p):.4f} dense) in {t_gen:.1f} s; Gram, eigh, "
+            f"cell factor and solve in {time.perf_counter() - t:.1f} s ({sol.info['iterations']} iterations)")
+    return {"csr": (rpd, cd, vd), "nnz": nnz, "A": A, "G": G, "w": w, "Vt": Vt, "rank": rank, "U": U,
+            "psi": sol.lam[0].contiguous(), "labels": labels, "n": n, "p": p, "r": r}
 
 
 def cpu_baseline(V, psi, k, n_clusters=40, seed=3000, per_cluster=8, edge=32):
@@ -123,25 +164,19 @@ def cpu_baseline(V, psi, k, n_clusters=40, seed=3000, per_cluster=8, edge=32):
                       f"{n / (rows.size / dt) / 3600:.1f} h (extrapolated)"}
 
 
-def stages(g, n, p, r, multimodal=True):
-    """Gram, eigendecomposition, cell factor and solve at the workload's shape."""
-    import numpy as np
+def stages(g, inp, multimodal=True):
+    """Gram, eigendecomposition, cell factor and solve of the chain inputs, each
+    timed again on its own; then the Skeptic, the shared-cell path, the tensor
+    solve and a full-rank gene axis."""
     import torch
 
-    import synth
+    n, p, r = inp["n"], inp["p"], inp["r"]
+    rpd, cd, vd = inp["csr"]
+    nnz = inp["nnz"]
+    A = inp["A"]
     out = {"input": f"{n} x {p} log1p(NB counts), 5% nonzeros, 40 Zipf-sized clusters, rank-8 cell "
-                    f"factor (the NB/log1p recipe drawn on the GPU, seed 3000)", "r": r}
-    t0 = time.perf_counter()
-    labels = synth.cluster_labels(n, 40, True, 3000)
-    beta0 = synth._calibrate_beta0(0.05, p, 40, labels, 3000)
-    del labels
-    A = synth.cell_factor_gpu(n, 3000)
-    rpd, cd, vd = synth.nb_log1p_csr_gpu(n, p, 40, True, 3000, beta0=beta0, A=A)
-    nnz = int(rpd[-1])
-    out["nnz"] = nnz
-    log(f"stages: generated {nnz} nonzeros ({nnz / (n * p):.4f} dense) in {time.perf_counter() - t0:.1f} s")
-    torch.cuda.empty_cache()
-    G = torch.empty(p, p, dtype=torch.float32, device="cuda")
+                    f"factor (the NB/log1p recipe drawn on the GPU, seed 3000)", "r": r, "nnz": nnz}
+    G = inp.pop("G")
 
     def timed(fn, reps):
         best = None
@@ -190,6 +225,8 @@ def stages(g, n, p, r, multimodal=True):
         out["gram"][path] = rec
     log(f"stages: gram {wall * 1e3:.1f} ms ({out['gram']['achieved']:.2f} TF/s algorithmic); forced paths: "
         f"dense {out['gram']['dense']['ms']:.1f} ms, sparse {out['gram']['sparse']['ms']:.1f} ms")
+    del inp["Vt"]
+    torch.cuda.empty_cache()
     wall, kms, cnt, res = timed(lambda: g.eigh_small(G), 1)
     w, Vt, rank = res
     out["eigh"] = {"ms": wall * 1e3, "solver_ms": kms, "p": p, "rank": rank,
@@ -211,7 +248,6 @@ def stages(g, n, p, r, multimodal=True):
     out["solve"] = {"ms": wall * 1e3, "r_c": r, "r_g": rank, **{k: sol.info[k] for k in
                                                             ("iterations", "kkt", "n_pinned")}}
     log(f"stages: solve {wall * 1e3:.1f} ms, {sol.info['iterations']} iterations")
-    out["chain_recompose"] = chain_recompose(g, U, sol.lam[0].contiguous(), 10)
     # the Nonparanormal Skeptic of the same matrix kept sparse (S + 1 z^T), and
     # the Gram of the transform through the rank-two correction
     del Vt, U
@@ -232,6 +268,7 @@ def stages(g, n, p, r, multimodal=True):
     if multimodal:
         out["shared_cells"] = shared_cells(g, n, p, rpd, cd, vd, nnz, Eg, r, A)
     del rpd, cd, vd, A
+    inp.clear()
     torch.cuda.empty_cache()
     out["tensor_solve"] = tensor_solve(g)
     out["gene_axis_recompose"] = gene_axis_recompose(g)
@@ -289,35 +326,6 @@ def library_spectra(g, tensors):
         E.append(spectrum(np.moveaxis(X, 2, 0).reshape(X.shape[2], -1).T))
         mods.append((0, 1 + 2 * i, 2 + 2 * i))
     return E, mods
-
-
-def chain_recompose(g, U, psi, k, prec="bf16", steps=3):
-    """The metric's recomposition on the chain's own output: the cell factor
-    from gmgm_sketch of the CSR above and psi from gmgm_solve_eigs of its
-    spectra."""
-    import torch
-    n, r = U.shape
-    out = (torch.empty(n + 1, dtype=torch.int64, device="cuda"), torch.empty(n * k, dtype=torch.int32, device="cuda"),
-           torch.empty(n * k, dtype=torch.float32, device="cuda"))
-    g.recompose_topk(U, psi, k, prec=prec, out=out)
-    g.sync()
-    g.kernel_times()
-    g.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        g.recompose_topk(U, psi, k, prec=prec, out=out, check=False)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    g.set_timing(False)
-    sweep_ms, cnt = g.kernel_times()
-    sweep_ms /= max(cnt, 1)
-    st = g.recompose_topk(U, psi, k, prec=prec, out=out, stats=True).stats
-    flops = 2.0 * r * n * n
-    log(f"stages: chain recompose {dt * 1e3:.1f} ms/step, sweep {sweep_ms:.1f} ms, stats {st}")
-    return {"input": "cell factor of the NB/log1p matrix above (gmgm_sketch, r = %d) and its solved psi" % r,
-            "rows_per_s": n / dt, "ms_per_step": dt * 1e3, "sweep_ms": sweep_ms,
-            "sweep_frac_of_peak": flops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], "stats": st}
 
 
 def gene_axis_recompose(g, n=20_000, k=10, seed=3000):
@@ -431,7 +439,7 @@ def threshold_leg(g, Vd, pd, topk_out, k, prec, n, r, steps=5, warmup=2):
     sweep_ms /= steps            # both sweeps of a call (all rows, then the rows with many candidates)
     flops = 2.0 * r * n * n
     log(f"threshold {thr:.4g}: {dt * 1e3:.2f} ms/step, sweep {sweep_ms:.2f} ms, nnz {res.nnz}")
-    return {"thr": thr, "rule": "median over rows of the k-th largest |Psi| (about k kept per row)",
+    return {"thr": thr, "rule": "median over rows of the k-th largest |Psi| (half the rows keep at least k)",
             "rows_per_s": n / dt, "ms_per_step": dt * 1e3, "sweep_ms": sweep_ms,
             "sweep_tflops": flops / (sweep_ms * 1e-3) / 1e12,
             "sweep_frac_of_peak": flops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], "nnz": res.nnz,
@@ -490,6 +498,10 @@ def main():
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timings")
     ap.add_argument("--no-multimodal", action="store_true", help="skip the shared-cell-axis stage")
     ap.add_argument("--profile-run", action="store_true", help="one step + a 1 GiB copy, no JSON")
+    ap.add_argument("--workload", default="chain", choices=["chain", "proxy"],
+                    help="chain: the cell factor and psi the path computes from the generated 1M x 20k "
+                         "counts; proxy: the stand-in factor and spectrum")
+    ap.add_argument("--no-standin", action="store_true", help="skip timing the stand-in factor beside the chain")
     ap.add_argument("--sources-sha", action="store_true", help="print the SHA-256 of the sweep's sources")
     ap.add_argument("--tensor-solve-only", action="store_true",
                     help="only the tensor-variate eigenvalue solve at the COIL-20 shape (its own JSON line)")
@@ -517,10 +529,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     g.load()
     n, r, k = args.n, args.r, args.k
-    log(f"generating workload n={n} r={r}")
-    V, psi = workload(n, r)
-    Vd = torch.from_numpy(V).cuda()
-    pd = torch.from_numpy(psi).cuda()
+    inp = None
+    if args.workload == "chain":
+        log(f"building the path's inputs n={n} p=20000 r={r}")
+        inp = chain_inputs(g, n, 20_000, r)
+        Vd, pd = inp["U"], inp["psi"]
+    else:
+        log(f"generating the stand-in workload n={n} r={r}")
+        V, psi = workload(n, r)
+        Vd = torch.from_numpy(V).cuda()
+        pd = torch.from_numpy(psi).cuda()
     if args.profile_run:
         profile_run(g, Vd, pd, k, args.prec, n)
         return
@@ -554,14 +572,12 @@ def main():
     log(f"{args.prec}: {step_s * 1e3:.2f} ms/step, sweep {sweep_ms:.2f} ms, stats {st_main}")
 
     flops = 2.0 * r * n * n
-    traffic, traffic_note = profiled_sweep_traffic(args.prec, n, r, k)
+    traffic, traffic_note = profiled_sweep_traffic(args.prec, n, r, k, args.workload)
     result = {
         "metric": METRIC, "value": n / step_s, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": "cell-axis recomposition + top-k at the 1M cells x 20k genes workload's "
-                               "shape (n=1,000,000, r=100, k=10) on a stand-in cell factor (orthonormal, "
-                               "40 Zipf clusters) and psi = 1/E of a Marchenko-Pastur + spike spectrum",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "n": n, "r": r, "k": k, "prec": args.prec, "global_batch": n, "seq_len": None,
                    "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "mfma", "kernel": "sweep_kernel",
@@ -594,14 +610,29 @@ def main():
     if "fp32" in result:
         result["recall_vs_fp32"] = result["fp32"][f"recall_of_{args.prec}_vs_fp32"]
         result["speedup_vs_fp32"] = result["fp32"]["ms_per_step"] / result["ms_per_step"]
+    if args.workload == "chain" and not args.no_standin:
+        # the stand-in factor used before the full chain was run here, for continuity
+        V0, psi0 = workload(n, r)
+        V0d, p0d = torch.from_numpy(V0).cuda(), torch.from_numpy(psi0).cuda()
+        del V0, psi0
+        Vd_m, pd_m = Vd, pd
+        Vd, pd = V0d, p0d
+        s0, sw0, st0 = run(args.prec, 3, 1, out_main)
+        Vd, pd = Vd_m, pd_m
+        result["stand_in_workload"] = {"input": WORKLOAD_TEXT["proxy"], "rows_per_s": n / s0,
+                                       "ms_per_step": s0 * 1e3, "sweep_ms": sw0, "stats": st0}
+        log(f"stand-in factor: {s0 * 1e3:.2f} ms/step, sweep {sw0:.2f} ms, stats {st0}")
+        del V0d, p0d
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on sampled rows)")
+        result["cpu_baseline"] = cpu_baseline(Vd.cpu().numpy(), pd.cpu().numpy(), k)
     if not args.no_stages:
         del out_main, ref
         torch.cuda.empty_cache()
-        result["stages"] = stages(g, n, 20_000, r,
-                                  multimodal=not args.no_multimodal)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on sampled rows)")
-        result["cpu_baseline"] = cpu_baseline(V, psi, k)
+        if inp is None:
+            inp = chain_inputs(g, n, 20_000, r)
+        del Vd, pd
+        result["stages"] = stages(g, inp, multimodal=not args.no_multimodal)
     print(json.dumps(result), flush=True)
 
 

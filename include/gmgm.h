@@ -429,7 +429,9 @@ typedef struct {
  *   max_iter     Newton iteration limit (>= 0).
  *   lambda_out   host array of n_axes device pointers, r_l FP64 each (written).
  *   info         host pointer or NULL.
- * The Schur system (sum of the hub axes' ranks) is limited to 2048 unknowns.
+ * The Schur system (sum of the hub axes' ranks) is limited to 32768 unknowns
+ * (factorised by one workgroup up to 2048, by rocSOLVER's Cholesky above;
+ * its nS^2 FP64 entries are workspace).
  * Synchronises (every iteration reads scalars back).  Returns GMGM_E_NOCONV
  * (outputs written, info filled) when tol is not reached in max_iter
  * iterations or the line search stalls; GMGM_E_DOMAIN for non-positive or

@@ -40,7 +40,8 @@ namespace gmgm_sv {
 
 constexpr int RED_THREADS = 1024;
 constexpr int MAX_AXES = 8;        // pair solver; axes of one modality (tensor solver)
-constexpr int MAX_HUB = 2048;
+constexpr int MAX_HUB = 32768;     // pair solver: unknowns of the Schur system
+constexpr int CHOL_ONE_WG = 2048;  // up to this size the Schur system is factorised by one workgroup
 constexpr int MAX_TAXES = 64;      // tensor solver: axes
 constexpr int MAX_DENSE = 8192;    // tensor solver: unknowns of the dense Newton system
 
@@ -963,7 +964,20 @@ struct Solver : Core {
     hipLaunchKernelGGL(schur_pin_kernel, dim3(nblk(nS), (unsigned)nS), dim3(256), 0, st, act_hub,
                        (int)nS, S, rhs);
     GMGM_HIP(c, hipMemsetAsync(flag, 0, sizeof(int), st));
-    hipLaunchKernelGGL(cholesky_solve_kernel, dim3(1), dim3(1024), 0, st, S, (int)nS, rhs, flag);
+    if (nS <= (size_t)CHOL_ONE_WG) {
+      hipLaunchKernelGGL(cholesky_solve_kernel, dim3(1), dim3(1024), 0, st, S, (int)nS, rhs, flag);
+    } else {
+      // larger systems: rocSOLVER's blocked Cholesky (S is symmetric and fully
+      // stored, so its row-major storage is its column-major one); a failed
+      // factorisation leaves a positive info in flag, as the kernel above does
+      void* hv;
+      GMGM_TRY(blas_handle(c, &hv));
+      rocblas_handle bh = (rocblas_handle)hv;
+      const rocblas_int n = (rocblas_int)nS;
+      if (rocsolver_dpotrf(bh, rocblas_fill_lower, n, S, n, flag) != rocblas_status_success ||
+          rocsolver_dpotrs(bh, rocblas_fill_lower, n, 1, S, n, rhs, n) != rocblas_status_success)
+        return set_err(c, GMGM_E_HIP, "rocSOLVER Cholesky failed in the Newton solve");
+    }
     for (int l : hub)
       hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, rhs + hoff[l],
                          g + ax[l].off, h + ax[l].off, act + ax[l].off, ax[l].r, d + ax[l].off);
