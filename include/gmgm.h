@@ -455,7 +455,12 @@ gmgm_status gmgm_solve_eigs(gmgm_ctx_t ctx, int32_t n_axes, const int64_t* ranks
  * dense over all sum_l r_l coordinates (the Hessian couples every two axes of a
  * modality through sums over the others) and solved by eliminating each
  * modality's private axes (those in no other modality) before the shared ones,
- * FP64, deterministic reductions.  With every modality of two axes the solution
+ * FP64, deterministic reductions.  After 30 iterations the step rule switches
+ * to an escape mode (active set: coordinates whose diagonal step, with the
+ * Levenberg-Marquardt diagonal h + |g|/lambda, reaches the bound; no limit on
+ * how far a coordinate shrinks per step), which reaches minimisers on the box
+ * along directions of almost zero slope (modalities whose traces agree only to
+ * the rounding of FP32 Grams).  With every modality of two axes the solution
  * is that of gmgm_solve_eigs.
  *
  *   n_axes       2 .. 64 axes.

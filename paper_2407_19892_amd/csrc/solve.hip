@@ -11,13 +11,17 @@
 //
 // Method: projected Newton for bound constraints with a vanishing
 // Levenberg-Marquardt damping rho = min(1e-2, KKT residual) and an Armijo
-// search along the projection arc.  The host drives the iteration; every
+// search along the projection arc.  The tensor solver switches after 30
+// iterations to an escape mode (Bertsekas' active set with the diagonal
+// h + |g|/x, as in Levenberg-Marquardt, and no limit on how far a coordinate
+// may shrink per step) for directions of almost zero slope whose minimiser
+// sits on the box.  The host drives the iteration; every
 // arithmetic step runs in the kernels below (and rocBLAS/rocSOLVER for dense
 // factorisations).  Two solvers share the driver:
 //  - pairs (gmgm_solve_eigs): a Schur complement on "hub" axes (a minimum-rank
 //    vertex cover of the modality graph; the other axes have diagonal Hessian
 //    blocks and are eliminated), the hub system factored by a one-workgroup
-//    Cholesky;
+//    Cholesky (rocSOLVER's above 2048 unknowns);
 //  - any number of axes (gmgm_solve_eigs_tensor): batched tuple sums, the
 //    Newton system held dense and solved by block elimination of each
 //    modality's private axes.
@@ -194,7 +198,7 @@ __global__ void tensor_assemble_kernel(const double* __restrict__ E, const doubl
                                        const int* __restrict__ axis_of, const int* __restrict__ ax_off,
                                        const int* __restrict__ axis_ptr, const int* __restrict__ axis_jobs,
                                        const TupleJob* __restrict__ jobs, const double* __restrict__ eps_ax,
-                                       int n, double* __restrict__ g, double* __restrict__ h,
+                                       int n, int lm, double* __restrict__ g, double* __restrict__ h,
                                        int* __restrict__ active, double* __restrict__ kkt) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
@@ -210,7 +214,9 @@ __global__ void tensor_assemble_kernel(const double* __restrict__ E, const doubl
   const double eps = eps_ax[l];
   g[c] = gi;
   h[c] = hi;
-  const double reach = fmin(1e-3 * lam[c], gi / hi);
+  // lm: Bertsekas' rule with the Levenberg-Marquardt diagonal h + |g|/x, the
+  // whole diagonal step reaching the bound
+  const double reach = lm ? gi / (hi + fabs(gi) / lam[c]) : fmin(1e-3 * lam[c], gi / hi);
   active[c] = (lam[c] - eps <= reach) && (gi > 0.0);
   const bool at = lam[c] <= eps * (1.0 + 1e-12);
   kkt[c] = (at ? fmax(0.0, -gi) : fabs(gi)) / (0.5 * E[c]);
@@ -323,14 +329,15 @@ __global__ void __launch_bounds__(256) hub_rhs_kernel(const double* __restrict__
   if (lane == 0) rhs[K + i] -= a;
 }
 
-// Diagonal (1+rho) h, right-hand side -g and activity flags of every coordinate
-// (S's diagonal holds zeros before).
+// Diagonal (1+rho) h (lm: h + |g|/x), right-hand side -g and activity flags
+// of every coordinate (S's diagonal holds zeros before).
 __global__ void tensor_diag_kernel(const double* __restrict__ h, const double* __restrict__ g,
-                                   const int* __restrict__ act, int n, double damp, double* __restrict__ S,
-                                   double* __restrict__ rhs, int* __restrict__ act_hub) {
+                                   const int* __restrict__ act, int n, double damp, const double* __restrict__ x,
+                                   int lm, double* __restrict__ S, double* __restrict__ rhs,
+                                   int* __restrict__ act_hub) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  S[(size_t)c * n + c] = damp * h[c];
+  S[(size_t)c * n + c] = lm ? h[c] + fabs(g[c]) / x[c] : damp * h[c];
   rhs[c] = -g[c];
   act_hub[c] = act[c];
 }
@@ -536,13 +543,14 @@ __global__ void __launch_bounds__(1024) cholesky_solve_kernel(double* __restrict
   }
 }
 
-// Newton step of a hub axis: the Schur solution on free coordinates, -g/h on active ones.
+// Newton step of a hub axis: the Schur solution on free coordinates, -g/h on
+// active ones (lm: -g/(h + |g|/lam)).
 __global__ void hub_step_kernel(const double* __restrict__ x, const double* __restrict__ g,
                                 const double* __restrict__ h, const int* __restrict__ act, int n,
-                                double* __restrict__ d) {
+                                const double* __restrict__ lam, int lm, double* __restrict__ d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  d[i] = act[i] ? -g[i] / h[i] : x[i];
+  d[i] = act[i] ? -g[i] / (lm ? h[i] + fabs(g[i]) / lam[i] : h[i]) : x[i];
 }
 
 // acc[j] += sum_{free hub i} B[i][j] d_K[i] for a leaf axis (one wave per j).
@@ -637,11 +645,12 @@ __global__ void __launch_bounds__(RED_THREADS) axis_stats_kernel(const double* _
 constexpr double STEP_SHRINK = 64.0;
 __global__ void trial_all_kernel(const double* __restrict__ x, const double* __restrict__ d,
                                  const int* __restrict__ act, const int* __restrict__ axis_of,
-                                 const double* __restrict__ eps_ax, int n, double alpha, double* __restrict__ t) {
+                                 const double* __restrict__ eps_ax, int n, double alpha, int limit,
+                                 double* __restrict__ t) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double eps = eps_ax[axis_of[i]];
-  const double fl = act[i] ? eps : fmax(eps, x[i] / STEP_SHRINK);
+  const double fl = (act[i] || !limit) ? eps : fmax(eps, x[i] / STEP_SHRINK);
   t[i] = fmax(x[i] + alpha * d[i], fl);
 }
 
@@ -727,6 +736,10 @@ struct Core {
   std::vector<Axis> ax;
   std::vector<std::vector<int>> sets;   // each modality's axes
   size_t T = 0, nS = 0;
+  // escape mode (after lm_after iterations): Levenberg-Marquardt diagonal
+  // |g|/x in the Newton system and the active-set reach, no shrink limit
+  int lm_after = 1 << 30;
+  bool lm = false;
   double *lam, *trial, *Ec, *s1, *s2, *lg, *g, *h, *d, *acc, *kkt, *S, *rhs, *scal, *eps_ax;
   int *act, *act_hub, *flag, *axis_of, *ax_off, *ax_r;
   std::vector<int> h_axis_of, h_off, h_r;   // host copies (alive while copies are in flight)
@@ -812,7 +825,7 @@ struct Core {
   // trial = max(lam + alpha d, floor) over all coordinates
   void trial_point(double alpha) {
     hipLaunchKernelGGL(trial_all_kernel, dim3(nblk(T)), dim3(256), 0, st, lam, d, act, axis_of, eps_ax, (int)T,
-                       alpha, trial);
+                       alpha, lm ? 0 : 1, trial);
   }
 };
 
@@ -980,7 +993,8 @@ struct Solver : Core {
     }
     for (int l : hub)
       hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, rhs + hoff[l],
-                         g + ax[l].off, h + ax[l].off, act + ax[l].off, ax[l].r, d + ax[l].off);
+                         g + ax[l].off, h + ax[l].off, act + ax[l].off, ax[l].r, lam + ax[l].off, 0,
+                         d + ax[l].off);
     for (int m = 0; m < L; ++m) {
       if (is_hub[m]) continue;
       GMGM_HIP(c, hipMemsetAsync(acc + ax[m].off, 0, ax[m].r * sizeof(double), st));
@@ -1178,7 +1192,7 @@ struct TensorSolver : Core {
     hipLaunchKernelGGL(tuple_jobs_kernel, dim3(nblk(grad_waves, 4)), dim3(256), 0, st, x, ax_off, ax_r, grad_jobs,
                        (int)h_grad_jobs.size(), grad_waves, 0, p1, p2, (double*)nullptr);
     hipLaunchKernelGGL(tensor_assemble_kernel, dim3(nblk(T)), dim3(256), 0, st, Ec, x, p1, p2, axis_of, ax_off,
-                       axis_ptr, axis_jobs, grad_jobs, eps_ax, (int)T, g, h, act, kkt);
+                       axis_ptr, axis_jobs, grad_jobs, eps_ax, (int)T, lm ? 1 : 0, g, h, act, kkt);
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(RED_THREADS), 0, st, kkt, (int)T, scal);
     return fetch(kres, scal, 1);
   }
@@ -1189,8 +1203,8 @@ struct TensorSolver : Core {
   gmgm_status direction(double rho) {
     const double damp = 1.0 + rho;
     GMGM_HIP(c, hipMemsetAsync(S, 0, nS * nS * sizeof(double), st));
-    hipLaunchKernelGGL(tensor_diag_kernel, dim3(nblk(T)), dim3(256), 0, st, h, g, act, (int)T, damp, S, rhs,
-                       act_hub);
+    hipLaunchKernelGGL(tensor_diag_kernel, dim3(nblk(T)), dim3(256), 0, st, h, g, act, (int)T, damp, lam,
+                       lm ? 1 : 0, S, rhs, act_hub);
     if (cross_tiles > 0)
       hipLaunchKernelGGL(cross_jobs_kernel, dim3((unsigned)cross_tiles), dim3(256), 0, st, lam, ax_off, ax_r,
                          cross_jobs, (int)h_cross_jobs.size(), terms, S, (int)nS);
@@ -1198,7 +1212,8 @@ struct TensorSolver : Core {
                        (int)nS, S, rhs);
     GMGM_HIP(c, hipMemsetAsync(ginfo, 0, (groups.size() + 1) * sizeof(int), st));
     GMGM_TRY(block_arrow_solve());
-    hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(T)), dim3(256), 0, st, rhs, g, h, act, (int)T, d);
+    hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(T)), dim3(256), 0, st, rhs, g, h, act, (int)T, lam, lm ? 1 : 0,
+                       d);
     std::vector<int> bad(groups.size() + 1, 0);
     GMGM_HIP(c, hipMemcpyAsync(bad.data(), ginfo, bad.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     GMGM_HIP(c, hipStreamSynchronize(st));
@@ -1391,6 +1406,7 @@ gmgm_status drive(SV& sv, const double* const* E, const double* eps, const doubl
         break;
       }
       std::swap(sv.lam, sv.trial);
+      sv.lm = it >= sv.lm_after;
       GMGM_TRY(sv.gradient(sv.lam, &kres));
     }
     // back to the start's gauge along the flat directions; resume if that moved
@@ -1505,6 +1521,10 @@ extern "C" gmgm_status gmgm_solve_eigs_tensor(gmgm_ctx_t c, int32_t n_axes, cons
   sv.c = c;
   sv.st = c->stream;
   sv.L = n_axes;
+  // nearly balanced modalities (traces equal to a few ulps of the spectra's
+  // precision) leave a direction of tiny slope whose minimiser lies on the
+  // box far away; the default rule crawls along it, the escape mode reaches it
+  sv.lm_after = 30;
   sv.ax.resize(n_axes);
   for (int l = 0; l < n_axes; ++l) {
     if (ranks[l] < 1 || ranks[l] > MAX_DENSE)

@@ -177,6 +177,21 @@ def test_coil_shape_all_components(lib):
     print("coil all components:", info["iterations"], "iterations", flush=True)
 
 
+@pytest.mark.parametrize("pert", [1e-10, pytest.param(1e-8, marks=pytest.mark.xfail(
+    reason="the escape mode's line search stops at KKT 1.2e-8 after 34 iterations on this case (open; the "
+           "library spectra of the COIL shape, imbalanced by ~5e-8, converge in 83)", strict=False))])
+def test_nearly_balanced_modality_reaches_the_box(lib, pert):
+    """A single modality whose axes' traces differ by `pert` relative (as
+    spectra from FP32 Grams of a balanced tensor do): the 21st-like shift
+    direction has a tiny slope and the minimiser sits on the box far along
+    it.  The GPU must converge there (the escape mode after 30 iterations)
+    and agree with the oracle, which pins one eigenvalue on two axes."""
+    E = low_rank_tensor_spectra((20, 32, 32), 4, seed=2)
+    E[1] = E[1] * (1 + pert)
+    prob, ref, lam, info = _check(lib, E, [(0, 1, 2)], f"nearly balanced {pert}")
+    assert info["iterations"] <= 120, info
+
+
 def test_order_of_axes_and_modalities_does_not_matter(lib):
     """The coordinate layout follows the order of the modalities and of their
     axes; the solution must not (within the parity bar)."""
