@@ -116,8 +116,9 @@ typedef struct {
  *               16 or 32, 0 picks 32 for BF16 / FP8 (a list covers a whole
  *               row) and 16 for FP32 (half a row).  Otherwise (the contraction
  *               streamed in chunks of 32; FP8 requests run with BF16
- *               operands): 32, 64 or 128, 0 picks the smallest that is at
- *               least 2k.
+ *               operands, and every request with FP32 operands when r > 4096,
+ *               where the BF16 bound certifies no row): 32, 64 or 128, 0
+ *               picks the smallest that is at least 2k.
  *   row_ptr_out (row_end - row_begin + 1) int64: row_ptr[t] = k * t.
  *   col_out     k * (row_end - row_begin) int32, ascending within a row.
  *   val_out     k * (row_end - row_begin) FP32: Psi_ij (signed), rounded
@@ -176,7 +177,8 @@ gmgm_status gmgm_recompose_topk_noalloc(gmgm_ctx_t ctx, int64_t n, int64_t r, co
  *   c_out       host double: c.
  *   kpad_out    host int32 or NULL: the padded MFMA depth for r (r > 128:
  *               the streamed sweep's, a multiple of 32, with FP8 requests
- *               reported for their BF16 operands).
+ *               reported for their BF16 operands and every request above
+ *               r = 4096 for FP32 operands, as the sweep runs them).
  * Host arithmetic only (no context, no device).  GMGM_E_ARG / GMGM_E_SHAPE
  * for a bad precision or rank.
  */

@@ -883,8 +883,14 @@ static bool topk_fast_path(int64_t r, int k, int cand_cap) {
 }
 
 // K-loop path: the contraction padded to a multiple of 32 (one chunk), FP8
-// requests served by the BF16 sweep.
-static int kl_prec(int prec) { return prec == P_F32 ? P_F32 : P_BF16; }
+// requests served by the BF16 sweep.  Above KL_BF16_MAX_R the BF16 bound
+// (which grows with ||W_i|| max_j ||V_j|| while the entries near the k-th do
+// not) certifies no row in practice (n = r = 20000: every row re-swept), so
+// the first sweep runs in FP32 whatever the request.
+constexpr int64_t KL_BF16_MAX_R = 4096;
+static int kl_prec(int prec, int64_t r) {
+  return (prec == P_F32 || r > KL_BF16_MAX_R) ? P_F32 : P_BF16;
+}
 static int kl_kpad(int64_t r) { return (int)ceil_div(r, 32) * 32; }
 
 // Arguments of gmgm_recompose_topk, checked before anything is launched.
@@ -927,7 +933,7 @@ static size_t topk_workspace_bound(int prec, int64_t n, int64_t r, int64_t row_b
                                    int smax, int k) {
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   if (!topk_fast_path(r, k, C)) {
-    const int pk = kl_prec(prec);
+    const int pk = kl_prec(prec, r);
     const int units = kl_kpad(r) / chunk_elems(pk) / 2;
     const int64_t rows = row_end - row_begin;
     const int n_vtiles = (int)ceil_div(n, 32);
@@ -1285,7 +1291,7 @@ static gmgm_status topk_general(gmgm_ctx* c, int64_t n, int64_t r, const float* 
                                 int64_t row_begin, int64_t row_end, int32_t k, int prec_in, int C, int smax,
                                 int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats) {
   hipStream_t st = c->stream;
-  const int prec = kl_prec(prec_in);
+  const int prec = kl_prec(prec_in, r);
   const int kpad = kl_kpad(r);
   const int units = kpad / chunk_elems(prec) / 2;
   const int64_t rows = row_end - row_begin;
@@ -1739,8 +1745,9 @@ extern "C" gmgm_status gmgm_significance_threshold(gmgm_ctx_t c, int64_t d_l, in
 extern "C" gmgm_status gmgm_rounding_bound(int32_t prec, int64_t r, double* c_out, int32_t* kpad_out) {
   if (prec < 0 || prec > 2 || !c_out) return GMGM_E_ARG;
   if (r < 1 || r > TOPK_MAX_R) return GMGM_E_SHAPE;
-  // r > 128 takes the K-loop sweep (FP8 requests run in BF16 there)
-  if (r > 128) prec = kl_prec(prec);
+  // r > 128 takes the K-loop sweep (FP8 requests run in BF16 there, every
+  // request in FP32 above 4096)
+  if (r > 128) prec = kl_prec(prec, r);
   const int kpad = r <= 128 ? kpad_for(prec, (int)r) : kl_kpad(r);
   *c_out = cprec_for(prec, kpad);
   if (kpad_out) *kpad_out = kpad;

@@ -176,3 +176,15 @@ def test_adversarial_rows_defeat_a_one_unit_bound_but_not_the_library_bound(g, k
     c, _ = g.rounding_bound("bf16", V.shape[1])
     ok_new, _ = _certify(approx, exact, k, cap, c * scale)
     assert not ok_new                                      # the library's bound sends the row on
+
+
+def test_large_rank_requests_report_the_precision_that_runs(g):
+    """Above r = 4096 the streamed sweep runs every request with FP32 operands
+    (the BF16 bound certifies no row there): the reported constant is FP32's."""
+    c32, k32 = g.rounding_bound("fp32", 5000)
+    for prec in ("bf16", "fp8"):
+        c, kpad = g.rounding_bound(prec, 5000)
+        assert (c, kpad) == (c32, k32)
+    cb, _ = g.rounding_bound("bf16", 4096)
+    assert cb > 4 * g.rounding_bound("fp32", 4096)[0]          # 4096 still runs BF16
+
