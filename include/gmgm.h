@@ -414,7 +414,11 @@ typedef struct {
  * shifted by +c and -c with equal traces) are fixed to the gauge of 1/E.  A
  * warm start is moved to that gauge, clipped to the box, and used only when
  * its NLL is not above that of 1/E.  Per iteration a free eigenvalue may
- * shrink by at most a factor 64.
+ * shrink by at most a factor 64.  After 30 iterations the step rule switches
+ * to an escape mode (active set: coordinates whose diagonal step, with the
+ * Levenberg-Marquardt diagonal h + |g|/lambda, reaches the bound; no shrink
+ * limit), which reaches minimisers on the box along directions of almost zero
+ * slope (axes whose traces agree only to rounding).
  *
  *   n_axes       2..8 axes.
  *   ranks        host, n_axes retained ranks r_l >= 1.
@@ -457,13 +461,9 @@ gmgm_status gmgm_solve_eigs(gmgm_ctx_t ctx, int32_t n_axes, const int64_t* ranks
  * dense over all sum_l r_l coordinates (the Hessian couples every two axes of a
  * modality through sums over the others) and solved by eliminating each
  * modality's private axes (those in no other modality) before the shared ones,
- * FP64, deterministic reductions.  After 30 iterations the step rule switches
- * to an escape mode (active set: coordinates whose diagonal step, with the
- * Levenberg-Marquardt diagonal h + |g|/lambda, reaches the bound; no limit on
- * how far a coordinate shrinks per step), which reaches minimisers on the box
- * along directions of almost zero slope (modalities whose traces agree only to
- * the rounding of FP32 Grams).  With every modality of two axes the solution
- * is that of gmgm_solve_eigs.
+ * FP64, deterministic reductions; the same escape mode after 30 iterations
+ * (modalities whose traces agree only to the rounding of FP32 Grams).  With
+ * every modality of two axes the solution is that of gmgm_solve_eigs.
  *
  *   n_axes       2 .. 64 axes.
  *   ranks, E, eps, warm, tol, max_iter, lambda_out, info: as for

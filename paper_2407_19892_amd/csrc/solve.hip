@@ -11,7 +11,7 @@
 //
 // Method: projected Newton for bound constraints with a vanishing
 // Levenberg-Marquardt damping rho = min(1e-2, KKT residual) and an Armijo
-// search along the projection arc.  The tensor solver switches after 30
+// search along the projection arc.  Both solvers switch after 30
 // iterations to an escape mode (Bertsekas' active set with the diagonal
 // h + |g|/x, as in Levenberg-Marquardt, and no limit on how far a coordinate
 // may shrink per step) for directions of almost zero slope whose minimiser
@@ -386,7 +386,7 @@ __global__ void pair_merge_kernel(int nx, int nsplit, const double* __restrict__
 // |g| / (E/2) when free, max(0, -g) / (E/2) at the bound.
 __global__ void assemble_kernel(const double* __restrict__ E, const double* __restrict__ lam,
                                 const double* __restrict__ s1, const double* __restrict__ s2,
-                                double eps, int n, double* __restrict__ g, double* __restrict__ h,
+                                double eps, int n, int lm, double* __restrict__ g, double* __restrict__ h,
                                 int* __restrict__ active, double* __restrict__ kkt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -395,14 +395,14 @@ __global__ void assemble_kernel(const double* __restrict__ E, const double* __re
   g[i] = gi;
   h[i] = hi;
   // coordinates within a diagonal-Newton step of their bound that want to go down
-  const double reach = fmin(1e-3 * lam[i], gi / hi);
+  const double reach = lm ? gi / (hi + fabs(gi) / lam[i]) : fmin(1e-3 * lam[i], gi / hi);
   active[i] = (lam[i] - eps <= reach) && (gi > 0.0);
   const bool at = lam[i] <= eps * (1.0 + 1e-12);
   kkt[i] = (at ? fmax(0.0, -gi) : fabs(gi)) / (0.5 * E[i]);
 }
 
 // Schur complement of a leaf axis m against hub axes K1 (rows) and K2 (columns):
-//   S[K1_i][K2_k] -= sum_{free j} B1[i][j] B2[k][j] / ((1+rho) h_m[j]),
+//   S[K1_i][K2_k] -= sum_{free j} B1[i][j] B2[k][j] / ((1+rho) h_m[j])   (lm: h_m + |g_m|/y),
 //   B[i][j] = 1/2 (x_i + y_j)^-2,
 // and, when with_rhs, rhs[K1_i] += sum_{free j} B1[i][j] g_m[j] / ((1+rho) h_m[j]).
 // A 16 x 16 tile of S per workgroup.
@@ -412,7 +412,7 @@ __global__ void assemble_kernel(const double* __restrict__ E, const double* __re
 __global__ void __launch_bounds__(256) schur_leaf_kernel(
     const double* __restrict__ x1, int n1, const double* __restrict__ x2, int n2,
     const double* __restrict__ ym, int nm, const int* __restrict__ act_m,
-    const double* __restrict__ hm, const double* __restrict__ gm, double damp,
+    const double* __restrict__ hm, const double* __restrict__ gm, double damp, int lm,
     double* __restrict__ part, double* __restrict__ rpart, int with_rhs) {
   __shared__ double b1[16][65], b2[16][65], w[64], wg[64];
   const int ti = threadIdx.x >> 4, tk = threadIdx.x & 15;
@@ -442,8 +442,9 @@ __global__ void __launch_bounds__(256) schur_leaf_kernel(
     if (threadIdx.x < 64) {
       const int j = j0 + threadIdx.x;
       const bool fr = j < je && !act_m[j];
-      w[threadIdx.x] = fr ? 1.0 / (damp * hm[j]) : 0.0;
-      wg[threadIdx.x] = fr ? gm[j] / (damp * hm[j]) : 0.0;
+      const double dj = fr ? (lm ? hm[j] + fabs(gm[j]) / ym[j] : damp * hm[j]) : 1.0;
+      w[threadIdx.x] = fr ? 1.0 / dj : 0.0;
+      wg[threadIdx.x] = fr ? gm[j] / dj : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
@@ -483,15 +484,16 @@ __global__ void schur_cross_kernel(const double* __restrict__ x1, int n1, int of
   S[(size_t)(off2 + k) * ldS + off1 + i] += b;
 }
 
-// Diagonal (1+rho) h and right-hand side -g of a hub axis; copies its activity flags
-// into hub order.
+// Diagonal (1+rho) h (lm: h + |g|/x) and right-hand side -g of a hub axis;
+// copies its activity flags into hub order.
 __global__ void schur_diag_kernel(const double* __restrict__ h, const double* __restrict__ g,
                                   const int* __restrict__ act, int n, int off, double damp,
+                                  const double* __restrict__ x, int lm,
                                   double* __restrict__ S, int ldS, double* __restrict__ rhs,
                                   int* __restrict__ act_hub) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  S[(size_t)(off + i) * ldS + off + i] += damp * h[i];
+  S[(size_t)(off + i) * ldS + off + i] += lm ? h[i] + fabs(g[i]) / x[i] : damp * h[i];
   rhs[off + i] = -g[i];
   act_hub[off + i] = act[i];
 }
@@ -574,10 +576,12 @@ __global__ void __launch_bounds__(256) leaf_partner_kernel(const double* __restr
 
 __global__ void leaf_step_kernel(const double* __restrict__ g, const double* __restrict__ h,
                                  const int* __restrict__ act, const double* __restrict__ acc,
-                                 int n, double damp, double* __restrict__ d) {
+                                 int n, double damp, const double* __restrict__ x, int lm,
+                                 double* __restrict__ d) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  d[j] = act[j] ? -g[j] / h[j] : (-g[j] - acc[j]) / (damp * h[j]);
+  const double dj = lm ? h[j] + fabs(g[j]) / x[j] : h[j];
+  d[j] = act[j] ? -g[j] / dj : (-g[j] - acc[j]) / (lm ? dj : damp * h[j]);
 }
 
 // *out = sum_i a[i] * (b ? b[i] : 1)  (one workgroup, fixed order)
@@ -931,7 +935,7 @@ struct Solver : Core {
         first = 0;
       }
       hipLaunchKernelGGL(assemble_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, Ec + ax[l].off,
-                         x + ax[l].off, s1 + ax[l].off, s2 + ax[l].off, ax[l].eps, ax[l].r,
+                         x + ax[l].off, s1 + ax[l].off, s2 + ax[l].off, ax[l].eps, ax[l].r, lm ? 1 : 0,
                          g + ax[l].off, h + ax[l].off, act + ax[l].off, kkt + ax[l].off);
     }
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(RED_THREADS), 0, st, kkt, (int)T, scal);
@@ -944,8 +948,8 @@ struct Solver : Core {
     GMGM_HIP(c, hipMemsetAsync(S, 0, nS * nS * sizeof(double), st));
     for (int l : hub)
       hipLaunchKernelGGL(schur_diag_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, h + ax[l].off,
-                         g + ax[l].off, act + ax[l].off, ax[l].r, (int)hoff[l], damp, S, (int)nS, rhs,
-                         act_hub);
+                         g + ax[l].off, act + ax[l].off, ax[l].r, (int)hoff[l], damp, lam + ax[l].off, lm ? 1 : 0,
+                         S, (int)nS, rhs, act_hub);
     for (auto& m : mods)
       if (is_hub[m.first] && is_hub[m.second]) {
         const int a = m.first, b = m.second;
@@ -968,8 +972,8 @@ struct Solver : Core {
           const int wr = K1 == K2 ? 1 : 0;
           hipLaunchKernelGGL(schur_leaf_kernel, dim3(nblk(ax[K2].r, 16), nblk(ax[K1].r, 16), (unsigned)nz),
                              dim3(256), 0, st, lam + ax[K1].off, ax[K1].r, lam + ax[K2].off, ax[K2].r,
-                             lam + ax[m].off, ax[m].r, act + ax[m].off, h + ax[m].off, g + ax[m].off, damp, part,
-                             rpart, wr);
+                             lam + ax[m].off, ax[m].r, act + ax[m].off, h + ax[m].off, g + ax[m].off, damp,
+                             lm ? 1 : 0, part, rpart, wr);
           hipLaunchKernelGGL(schur_leaf_merge_kernel, dim3(nblk(ax[K2].r), (unsigned)ax[K1].r), dim3(256), 0, st,
                              ax[K1].r, (int)hoff[K1], ax[K2].r, (int)hoff[K2], nz, part, rpart, S, (int)nS, rhs, wr);
         }
@@ -993,7 +997,7 @@ struct Solver : Core {
     }
     for (int l : hub)
       hipLaunchKernelGGL(hub_step_kernel, dim3(nblk(ax[l].r)), dim3(256), 0, st, rhs + hoff[l],
-                         g + ax[l].off, h + ax[l].off, act + ax[l].off, ax[l].r, lam + ax[l].off, 0,
+                         g + ax[l].off, h + ax[l].off, act + ax[l].off, ax[l].r, lam + ax[l].off, lm ? 1 : 0,
                          d + ax[l].off);
     for (int m = 0; m < L; ++m) {
       if (is_hub[m]) continue;
@@ -1006,7 +1010,8 @@ struct Solver : Core {
                            acc + ax[m].off);
       }
       hipLaunchKernelGGL(leaf_step_kernel, dim3(nblk(ax[m].r)), dim3(256), 0, st, g + ax[m].off,
-                         h + ax[m].off, act + ax[m].off, acc + ax[m].off, ax[m].r, damp, d + ax[m].off);
+                         h + ax[m].off, act + ax[m].off, acc + ax[m].off, ax[m].r, damp, lam + ax[m].off,
+                         lm ? 1 : 0, d + ax[m].off);
     }
     int bad = 0;
     GMGM_HIP(c, hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1491,6 +1496,7 @@ extern "C" gmgm_status gmgm_solve_eigs(gmgm_ctx_t c, int32_t n_axes, const int64
   }
   for (int l = 0; l < n_axes; ++l)
     if (!used[l]) return set_err(c, GMGM_E_ARG, "axis %d belongs to no modality", l);
+  sv.lm_after = 30;   // escape mode, as in the tensor solver (near-balanced pairs)
   sv.hub = hub_axes(sv.ax, sv.mods);
   sv.is_hub.assign(n_axes, 0);
   sv.hoff.assign(n_axes, 0);

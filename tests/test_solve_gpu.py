@@ -218,6 +218,15 @@ def test_from_perturbed_starts_against_the_independent_minimiser(lib, case):
         _compare(prob, ref, lam, info, f"{case} perturbed {t}")
 
 
+@pytest.mark.parametrize("pert", [1e-10, 1e-8])
+def test_nearly_balanced_pair_reaches_the_box(lib, pert):
+    """Two spectra equal up to a relative scale of `pert`: the shift direction
+    has a tiny slope and the minimiser lies on the box far along it (the
+    escape mode after 30 iterations gets there); parity with the oracle."""
+    e = synth.spectrum_proxy(300, 2000, 8, seed=5)
+    _check_against_oracle(lib, [e.copy(), e.copy() * (1 + pert)], [(0, 1)], f"nearly balanced {pert}")
+
+
 def test_both_axes_above_2048(lib):
     """A pair whose smaller axis has more than 2048 eigenvalues (the Schur
     system then goes through rocSOLVER's Cholesky): the FP64 KKT residual of
