@@ -32,7 +32,7 @@ class GmgmError(RuntimeError):
 class TopkStats(ctypes.Structure):
     _fields_ = [("cand_total", ctypes.c_int64), ("rows_fallback", ctypes.c_int64),
                 ("rows_near_tie", ctypes.c_int64), ("rows_exact", ctypes.c_int64),
-                ("mfma_flops", ctypes.c_double)]
+                ("mfma_flops", ctypes.c_double), ("symmetric", ctypes.c_int64)]
 
 
 class Csr(ctypes.Structure):
@@ -215,7 +215,7 @@ def recompose_topk(V, psi, k: int, prec: str = "bf16", row_begin: int = 0, row_e
     if st is not None:
         sd = {"cand_total": st.cand_total, "rows_fallback": st.rows_fallback,
               "rows_near_tie": st.rows_near_tie, "rows_exact": st.rows_exact,
-              "mfma_flops": st.mfma_flops}
+              "mfma_flops": st.mfma_flops, "symmetric": bool(st.symmetric)}
     return TopkResult(rp, col, val, sd)
 
 

@@ -52,7 +52,7 @@ void timing_stop(gmgm_ctx* c, hipEvent_t start);
 enum WsSlot : int {
   WS_VP = 0, WS_WP, WS_NORMS, WS_CAND, WS_MISC, WS_FALLBACK, WS_SCALES, WS_VP2, WS_WP2, WS_CAND2,
   WS_GRAM0, WS_GRAM1, WS_GRAM2, WS_GRAM3, WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_MLP0, WS_MLP1, WS_EIGH0,
-  WS_EIGH1, WS_SKETCH, WS_RF0, WS_RF1, WS_RF2, WS_THR0, WS_THR1, WS_THR2, WS_SKEP0, WS_SKEP1, WS_SKEP2,
+  WS_EIGH1, WS_SKETCH, WS_RF0, WS_RF1, WS_RF2, WS_THR0, WS_THR1, WS_THR2, WS_SKEP0, WS_SKEP1, WS_SKEP2, WS_SYM0, WS_SYM1, WS_SYM2,
   WS_COUNT
 };
 

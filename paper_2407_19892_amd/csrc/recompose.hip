@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -222,6 +223,13 @@ struct FinalArgs {
   int* fail_list;
   int* fail_count;
   unsigned long long* counters;   // [0] candidates, [1] near ties (certified rows); null: not counted
+  // symmetric form (contiguous rows from 0): further candidates of row i at
+  // [xoff[i], xoff[i + 1]) of (xidx, xval), every value above tau[i], the
+  // bound the row's list started from (null: none)
+  const long long* xoff;
+  const int* xidx;
+  const float* xval;
+  const float* tau;
 };
 
 constexpr int MAXK = 32;
@@ -264,6 +272,15 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
   const int64_t loc = i - a.row_begin;
   const int M = a.S * a.nsub * a.C;
   const int64_t cbase = slot * M;
+  // candidate q: list entries first, then the symmetric form's extra ones
+  int64_t xb = 0;
+  int MX = M;
+  if (a.xoff) {
+    xb = a.xoff[i];
+    MX = M + (int)(a.xoff[i + 1] - xb);
+  }
+  auto cand_j = [&](int q) { return q < M ? a.cidx[cbase + q] : a.xidx[xb + (q - M)]; };
+  auto cand_v = [&](int q) { return q < M ? a.cval[cbase + q] : a.xval[xb + (q - M)]; };
 
   for (int q = lane; q < a.r; q += 64) wrow[wave][q] = (double)a.V[i * a.r + q] * a.psi[q];
 
@@ -282,16 +299,16 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
 
   // k-th largest approximate key among the candidates
   int nvalid = 0;
-  for (int q = lane; q < M; q += 64) nvalid += a.cidx[cbase + q] != INVALID_J;
+  for (int q = lane; q < MX; q += 64) nvalid += cand_j(q) != INVALID_J;
   nvalid = wave_sum_i32(nvalid);
   unsigned long long prev = ~0ull;
   int found = 0;
   for (int t = 0; t < a.k; ++t) {
     unsigned long long best = 0;
-    for (int q = lane; q < M; q += 64) {
-      const int j = a.cidx[cbase + q];
+    for (int q = lane; q < MX; q += 64) {
+      const int j = cand_j(q);
       if (j == INVALID_J) continue;
-      const unsigned long long key = approx_key(a.cval[cbase + q], j);
+      const unsigned long long key = approx_key(cand_v(q), j);
       if (key < prev && key > best) best = key;
     }
     best = wave_max_u64(best);
@@ -305,13 +322,13 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
   // rescoring set R, compacted into LDS
   int rc = 0;
   __builtin_amdgcn_wave_barrier();
-  for (int base = 0; base < M; base += 64) {
+  for (int base = 0; base < MX; base += 64) {
     const int q = base + lane;
     bool take = false;
     int j = INVALID_J;
-    if (q < M) {
-      j = a.cidx[cbase + q];
-      take = j != INVALID_J && (double)a.cval[cbase + q] >= thr;
+    if (q < MX) {
+      j = cand_j(q);
+      take = j != INVALID_J && (double)cand_v(q) >= thr;
     }
     const unsigned long long mask = __ballot(take);
     const int pos = rc + __popcll(mask & ((1ull << lane) - 1ull));
@@ -387,6 +404,9 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
   if (ok) {
     tk = fabs(sel_v[wave][a.k - 1]);
     if (mout >= 0.0) ok = mout + beta < tk;
+    // symmetric form: values at or below the starting bound were dropped on
+    // both sides; none of them can reach the k-th exact value
+    if (a.tau) ok = ok && (double)a.tau[i] + beta < tk;
   }
   if (lane == 0) {
     if (a.counters) {   // statistics requested
@@ -869,6 +889,92 @@ __global__ void __launch_bounds__(256) thr_gather_kernel(const int* __restrict__
   }
 }
 
+// ------------------------------------------------------------ symmetric form
+// Bound of every row from a sweep over a sample of the columns: the exact FP64
+// values of the sample's k largest approximate |Psi_ij| (list entries 0 .. k-1,
+// k distinct columns), their minimum e_k, minus beta_i, rounded down to a
+// float.  The row's final k-th exact value T is at least e_k (k of its values
+// are at least e_k).  A value whose approximation is at most the bound is at
+// most bound + beta_i exactly; the finalize certifies a row only when
+// bound + beta_i < T, so no such value can be among its top k.  Rows without
+// a positive bound (fewer than k sample columns, a rounding margin as large as
+// the values) get +inf: the column side keeps nothing for them and their
+// certificate fails (they are re-swept in full).  Rows n .. 32 n_vtiles - 1
+// (padding) get +inf.  One wave per row, four rows per workgroup.
+__global__ void __launch_bounds__(256) tau_kernel(const float* __restrict__ cval, const int* __restrict__ cidx,
+                                                  int C, int k, const float* __restrict__ V,
+                                                  const double* __restrict__ psi, int r,
+                                                  const double* __restrict__ wnorm,
+                                                  const unsigned* __restrict__ vmax_bits, double cprec, int64_t n,
+                                                  float* __restrict__ tau) {
+  __shared__ double wrow[4][128];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  float out = INFINITY;
+  bool have = i < n;
+  if (have) have = cidx[i * C + k - 1] != INVALID_J;
+  if (have) {
+    for (int q = lane; q < r; q += 64) wrow[wave][q] = (double)V[i * r + q] * psi[q];
+    __builtin_amdgcn_wave_barrier();
+    // eight lanes per candidate: lane t of group g takes elements t, t + 8, ...
+    const int g = lane >> 3, t = lane & 7;
+    double ek = INFINITY;
+    for (int c0 = 0; c0 < k; c0 += 8) {
+      const int q = c0 + g;
+      double sum = 0.0;
+      if (q < k) {
+        const float* vj = V + (int64_t)cidx[i * C + q] * r;
+        for (int u = t; u < r; u += 8) sum = fma(wrow[wave][u], (double)vj[u], sum);
+      }
+#pragma unroll
+      for (int o = 4; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+      double m = q < k ? fabs(sum) : INFINITY;
+#pragma unroll
+      for (int o = 8; o < 64; o <<= 1) m = fmin(m, __shfl_xor(m, o, 64));
+      ek = fmin(ek, m);
+    }
+    const double beta = cprec * wnorm[i] * (double)__uint_as_float(*vmax_bits);
+    const double b = ek - beta;
+    if (b > 0.0 && b < 3.0e38) {
+      float f = (float)b;
+      if ((double)f > b) f = float_below(f);
+      out = f;
+    }
+  }
+  if (lane == 0) tau[i] = out;
+}
+
+// Column-side entries per row: count (one workgroup per pool chunk; chunks
+// never handed out have fill 0).
+__global__ void __launch_bounds__(256) cs_count_kernel(const int* __restrict__ cs_j, const int* __restrict__ fill,
+                                                       int64_t n, int* __restrict__ per_row) {
+  const int m = min(fill[blockIdx.x], CS_CHUNK);
+  const int64_t b = (int64_t)blockIdx.x * CS_CHUNK;
+  for (int e = threadIdx.x; e < m; e += blockDim.x) {
+    const int j = cs_j[b + e];
+    if (j >= 0 && j < n) atomicAdd(&per_row[j], 1);
+  }
+}
+
+// ... and scatter into per-row runs at off[j] (per_row counts down to zero;
+// the order inside a run is arbitrary, the finalize orders by value and index).
+__global__ void __launch_bounds__(256) cs_scatter_kernel(const int* __restrict__ cs_j, const int* __restrict__ cs_i,
+                                                         const float* __restrict__ cs_v, const int* __restrict__ fill,
+                                                         int64_t n, const int64_t* __restrict__ off,
+                                                         int* __restrict__ per_row, int* __restrict__ xidx,
+                                                         float* __restrict__ xval) {
+  const int m = min(fill[blockIdx.x], CS_CHUNK);
+  const int64_t b = (int64_t)blockIdx.x * CS_CHUNK;
+  for (int e = threadIdx.x; e < m; e += blockDim.x) {
+    const int j = cs_j[b + e];
+    if (j < 0 || j >= n) continue;
+    const int64_t pos = off[j] + atomicSub(&per_row[j], 1) - 1;
+    xidx[pos] = cs_i[b + e];
+    xval[pos] = cs_v[b + e];
+  }
+}
+
 }  // namespace gmgm_rc
 
 using namespace gmgm_rc;
@@ -973,7 +1079,8 @@ static size_t topk_workspace_bound(int prec, int64_t n, int64_t r, int64_t row_b
 
 static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
                              int64_t row_begin, int64_t row_end, int32_t k, int prec, int C, int smax,
-                             int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats);
+                             int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats,
+                             bool allow_sym = true);
 static gmgm_status topk_general(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
                                 int64_t row_begin, int64_t row_end, int32_t k, int prec, int C, int smax,
                                 int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats);
@@ -1052,14 +1159,171 @@ extern "C" gmgm_status gmgm_recompose_topk_noalloc(gmgm_ctx_t c, int64_t n, int6
   return s;
 }
 
+// The symmetric form serves BF16 calls for every row (n >= 1024, outside
+// allocation-free calls) when GMGM_RECOMPOSE_PATH=symmetric.  It is not the
+// default: at n = 1M, r = 100, k = 10 it executes 0.61 of the full sweep's
+// MFMA work but takes longer, the column-side test and appends costing more
+// than the tiles it skips.
+constexpr int SYM_STRIDE = 8;         // the bound pass visits every 8th column tile
+// Column-side pool: SYM_MARGIN times the entries expected (a value beats its
+// row's bound with probability about k SYM_STRIDE / n, the bound being near
+// the k-th largest of a 1/SYM_STRIDE sample), plus a chunk per wave.
+constexpr double SYM_MARGIN = 4.0;
+
+static bool sym_wanted(gmgm_ctx* c, int prec, int64_t n, int64_t row_begin, int64_t row_end) {
+  if (prec != P_BF16 || row_begin != 0 || row_end != n || c->arena || n < 1024) return false;
+  const char* e = getenv("GMGM_RECOMPOSE_PATH");
+  return e && !strcmp(e, "symmetric");
+}
+
+struct SymBufs {
+  const float* tau;
+  const int64_t* off;
+  const int* xidx;
+  const float* xval;
+};
+
+// The symmetric form of the sweep for every row (contiguous from 0), in three
+// steps:
+//  1. bound pass: the sweep over every SYM_STRIDE-th column tile with lists of
+//     16 (k <= 16) or 32, then the per-row bound tau (tau_kernel);
+//  2. symmetric sweep: workgroup b visits column tiles from its own first row
+//     tile on; its rows' lists start from tau, and values beyond its own block
+//     above tau[j] go to the column-side pool;
+//  3. the column-side entries grouped by row (count, prefix sum, scatter), for
+//     the finalize to take with the lists.
+// Sets *overflow (and does nothing else after step 2) when the pool ran out.
+static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, const double* psi, int r, int kpad,
+                             int C, int64_t gx, SymBufs* out, double* flops, bool* overflow) {
+  hipStream_t st = c->stream;
+  const int64_t n = sa.n;
+  const int n_vtiles = sa.n_vtiles;
+  const int64_t npad = (int64_t)n_vtiles * 32;
+  const int64_t w_rows = (int64_t)sa.n_wtiles * 32;
+  const int k = sa.k;
+  const int CA = k <= 16 ? 16 : 32;
+  SweepFn sweepA = pick_sweep_bf16_sample(kpad, CA);
+  SweepFn sweepS = pick_sweep_bf16_sym(kpad, C);
+  if (!sweepA || !sweepS) return set_err(c, GMGM_E_SHAPE, "no symmetric sweep variant for kpad = %d", kpad);
+  // pool size: workgroup b's 64-row waves see 32 T_b columns each
+  const double p_hit = std::min(1.0, (double)k * SYM_STRIDE / (double)n);
+  double expect = 0.0;
+  for (int64_t b = 0; b < gx; ++b) {
+    const int64_t tb = std::max<int64_t>(0, n_vtiles - (b + 1) * SW_WAVES * 2);
+    expect += SW_WAVES * 64.0 * 32.0 * (double)tb * p_hit;
+  }
+  const int64_t chunks = (int64_t)std::ceil(SYM_MARGIN * expect / CS_CHUNK) + gx * SW_WAVES;
+  const int64_t cap = chunks * CS_CHUNK;
+  if (cap >= ((int64_t)1 << 31) - CS_CHUNK) return set_err(c, GMGM_E_SHAPE, "column-side pool too large");
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  // WS_SYM0: tau | bound-pass lists (values, indices) | per-row counts | row
+  // offsets | info | pool counter + flag | chunk fills
+  const size_t o_tau = 0;
+  const size_t o_av = o_tau + up((size_t)npad * 4);
+  const size_t o_ai = o_av + up((size_t)w_rows * CA * 4);
+  const size_t o_cnt = o_ai + up((size_t)w_rows * CA * 4);
+  const size_t o_off = o_cnt + up((size_t)n * 4);
+  const size_t o_info = o_off + up((size_t)(n + 1) * 8);
+  const size_t o_flag = o_info + 256;
+  const size_t o_fill = o_flag + 256;
+  const size_t bytes0 = o_fill + up((size_t)chunks * 4);
+  void *w0, *w1;
+  GMGM_TRY(ws_get(c, WS_SYM0, bytes0, &w0));
+  GMGM_TRY(ws_get(c, WS_SYM1, (size_t)cap * 12, &w1));
+  char* b0 = (char*)w0;
+  float* tau = (float*)(b0 + o_tau);
+  float* av = (float*)(b0 + o_av);
+  int* ai = (int*)(b0 + o_ai);
+  int* per_row = (int*)(b0 + o_cnt);
+  int64_t* off = (int64_t*)(b0 + o_off);
+  long long* info = (long long*)(b0 + o_info);
+  unsigned* next = (unsigned*)(b0 + o_flag);
+  int* flag = (int*)(b0 + o_flag + 8);
+  int* fill = (int*)(b0 + o_fill);
+  int* cs_j = (int*)w1;
+  int* cs_i = cs_j + cap;
+  float* cs_v = (float*)(cs_i + cap);
+
+  // 1. bound pass
+  SweepArgs pa = sa;
+  pa.cval = av;
+  pa.cidx = ai;
+  pa.S = 1;
+  pa.tiles_per_split = n_vtiles;
+  pa.jt_stride = SYM_STRIDE;
+  sweepA<<<dim3((unsigned)gx, 1), dim3(SW_THREADS), 0, st>>>(pa);
+  hipLaunchKernelGGL(tau_kernel, dim3((unsigned)(npad / 4)), dim3(256), 0, st, (const float*)av, (const int*)ai,
+                     CA, k, V, psi, r, sa.wnorm, sa.vmax_bits, sa.cprec, n, tau);
+  // 2. symmetric sweep (pool counter, flag and chunk fills cleared first)
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)ceil_div(chunks + 64, 256)), dim3(256), 0, st,
+                     (unsigned*)next, (int)(256 / 4 + chunks));
+  SweepArgs sy = sa;
+  sy.S = 1;
+  sy.tiles_per_split = n_vtiles;
+  sy.tau = tau;
+  sy.cs_j = cs_j;
+  sy.cs_i = cs_i;
+  sy.cs_v = cs_v;
+  sy.cs_next = next;
+  sy.cs_cap = (int)cap;
+  sy.cs_fill = fill;
+  sy.cs_overflow = flag;
+  hipEvent_t t0 = timing_start(c);
+  sweepS<<<dim3((unsigned)gx, 1), dim3(SW_THREADS), 0, st>>>(sy);
+  timing_stop(c, t0);
+  // 3. group the column side by row
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, (unsigned*)per_row,
+                     (int)n);
+  hipLaunchKernelGGL(cs_count_kernel, dim3((unsigned)chunks), dim3(256), 0, st, (const int*)cs_j,
+                     (const int*)fill, n, per_row);
+  hipLaunchKernelGGL(thr_scan_kernel, dim3(1), dim3(1024), 0, st, (const int*)per_row, n, off, info);
+  GMGM_HIP(c, hipGetLastError());
+  long long h[2];
+  int hf = 0;
+  GMGM_HIP(c, hipMemcpyAsync(h, info, 16, hipMemcpyDeviceToHost, st));
+  GMGM_HIP(c, hipMemcpyAsync(&hf, flag, 4, hipMemcpyDeviceToHost, st));
+  GMGM_HIP(c, hipStreamSynchronize(st));
+  // executed MFMA work: the bound pass over its tiles, the symmetric sweep
+  // over the column tiles from each workgroup's first row tile on
+  const double per_tile = 2.0 * 32.0 * 32.0 * kpad;
+  double tiles = (double)sa.n_wtiles * (double)ceil_div(n_vtiles, SYM_STRIDE);
+  for (int64_t b = 0; b < gx; ++b) {
+    const int64_t t_lo = b * SW_WAVES * 2;
+    const int64_t wt = std::min<int64_t>(SW_WAVES * 2, sa.n_wtiles - t_lo);
+    tiles += (double)wt * (double)(n_vtiles - t_lo);
+  }
+  *flops = per_tile * tiles;
+  if (hf) {
+    *overflow = true;
+    return GMGM_OK;
+  }
+  void* w2;
+  const long long tot = std::max<long long>(h[0], 1);
+  GMGM_TRY(ws_get(c, WS_SYM2, (size_t)tot * 8, &w2));
+  int* xidx = (int*)w2;
+  float* xval = (float*)(xidx + tot);
+  hipLaunchKernelGGL(cs_scatter_kernel, dim3((unsigned)chunks), dim3(256), 0, st, (const int*)cs_j,
+                     (const int*)cs_i, (const float*)cs_v, (const int*)fill, n, (const int64_t*)off, per_row, xidx,
+                     xval);
+  GMGM_HIP(c, hipGetLastError());
+  out->tau = tau;
+  out->off = off;
+  out->xidx = xidx;
+  out->xval = xval;
+  *overflow = false;
+  return GMGM_OK;
+}
+
 static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, const double* psi,
                              int64_t row_begin, int64_t row_end, int32_t k, int prec, int C, int smax,
-                             int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats) {
+                             int64_t* row_ptr_out, int32_t* col_out, float* val_out, gmgm_topk_stats* stats,
+                             bool allow_sym) {
   GMGM_HIP(c, hipSetDevice(c->device));
   if (!topk_fast_path(r, k, C))
     return topk_general(c, n, r, V, psi, row_begin, row_end, k, prec, C, smax, row_ptr_out, col_out, val_out,
                         stats);
   hipStream_t st = c->stream;
+  const bool sym = allow_sym && sym_wanted(c, prec, n, row_begin, row_end);
 
   const int kpad = kpad_for(prec, (int)r);
   SweepFn sweep = pick_sweep(prec, kpad, C);
@@ -1074,7 +1338,7 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
   const int64_t w_lo = (int64_t)rt_begin * 32;
   const int64_t w_rows = (int64_t)n_wtiles * 32;
   const int64_t gx = ceil_div(n_wtiles, (int64_t)SW_WAVES * TI);
-  const int S = pick_splits(gx, n_vtiles, smax, 1024);
+  const int S = sym ? 1 : pick_splits(gx, n_vtiles, smax, 1024);
   const int tps = (int)ceil_div(n_vtiles, S);
 
   // ---- workspace
@@ -1143,9 +1407,20 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
   sa.w_lo = w_lo;
   sa.cprec = cprec_for(prec, kpad);
   sa.k = k;
-  hipEvent_t t0 = timing_start(c);
-  sweep<<<dim3((unsigned)gx, (unsigned)S), dim3(SW_THREADS), 0, st>>>(sa);
-  timing_stop(c, t0);
+  double flops = 0.0;
+  SymBufs symb{};
+  if (sym) {
+    bool overflow = false;
+    GMGM_TRY(sym_sweep(c, sa, V, psi, (int)r, kpad, C, gx, &symb, &flops, &overflow));
+    if (overflow)   // the column side outgrew its pool: the full sweep instead
+      return topk_impl(c, n, r, V, psi, row_begin, row_end, k, prec, C, smax, row_ptr_out, col_out, val_out,
+                       stats, false);
+  } else {
+    hipEvent_t t0 = timing_start(c);
+    sweep<<<dim3((unsigned)gx, (unsigned)S), dim3(SW_THREADS), 0, st>>>(sa);
+    timing_stop(c, t0);
+    flops = 2.0 * (double)w_rows * 32.0 * n_vtiles * kpad;
+  }
 
   FinalArgs fa{};
   fa.cval = A.cval;
@@ -1171,11 +1446,16 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
   fa.fail_list = list1;
   fa.fail_count = cnt1;
   fa.counters = stats ? counters : nullptr;   // counted only when asked for
+  if (sym) {
+    fa.xoff = (const long long*)symb.off;
+    fa.xidx = symb.xidx;
+    fa.xval = symb.xval;
+    fa.tau = symb.tau;
+  }
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, st, fa);
   hipLaunchKernelGGL(row_ptr_kernel, dim3((unsigned)ceil_div(rows + 1, 256)), dim3(256), 0, st,
                      row_ptr_out, rows, k);
   GMGM_HIP(c, hipGetLastError());
-  double flops = 2.0 * (double)w_rows * 32.0 * n_vtiles * kpad;
 
   // ---- stage B: rows stage A could not certify are re-swept with finer operands
   int h1 = 0, h2 = 0;
@@ -1218,6 +1498,7 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
         stats->rows_fallback = h1;
         stats->rows_exact = h1;
         stats->mfma_flops = flops;
+        stats->symmetric = 0;
       }
       return GMGM_OK;
     }
@@ -1248,6 +1529,10 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
     sb.cprec = cprec_for(precB, kpadB);
     sweepB<<<dim3((unsigned)gxB, (unsigned)SB), dim3(SW_THREADS), 0, st>>>(sb);
     FinalArgs fb = fa;
+    fb.xoff = nullptr;   // whole rows: no symmetric-form extras
+    fb.xidx = nullptr;
+    fb.xval = nullptr;
+    fb.tau = nullptr;
     fb.cval = B.cval;
     fb.cidx = B.cidx;
     fb.C = CB;
@@ -1280,6 +1565,7 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
     stats->rows_fallback = h1;
     stats->rows_exact = h2;
     stats->mfma_flops = flops;
+    stats->symmetric = sym ? 1 : 0;
   }
   return GMGM_OK;
 }
@@ -1466,6 +1752,7 @@ static gmgm_status topk_general(gmgm_ctx* c, int64_t n, int64_t r, const float* 
     stats->rows_fallback = h1;
     stats->rows_exact = h_exact;
     stats->mfma_flops = flops;
+    stats->symmetric = 0;
   }
   return GMGM_OK;
 }

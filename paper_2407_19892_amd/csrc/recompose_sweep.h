@@ -62,7 +62,25 @@ struct SweepArgs {
   int capt;
   int* tcount;
   const long long* toff;  // threshold mode, listed rows: candidate offsets per slot (null: slot * capt)
+  // column tiles visited: jt0, jt0 + jt_stride, ... (0 or 1: every tile)
+  int jt_stride;
+  // symmetric form: tau[j] (n_vtiles * 32 entries) is a lower bound of row
+  // j's final cut lowered by its rounding margin (+inf: none; padding +inf);
+  // the row's own list starts from it, and values Psi_ij of the column side
+  // above tau[j] go to a shared pool as (j, i, |Psi_ij|): a wave takes
+  // CS_CHUNK entries at a time (cs_next counts the entries handed out, up to
+  // cs_cap) and records how many of a chunk it filled in cs_fill[chunk]
+  const float* tau;
+  int* cs_j;
+  int* cs_i;
+  float* cs_v;
+  unsigned* cs_next;
+  int cs_cap;             // below 2^31 - CS_CHUNK
+  int* cs_fill;
+  int* cs_overflow;       // set to 1 when the pool ran out (entries were lost)
 };
+
+constexpr int CS_CHUNK = 2048;   // column-side pool entries a wave takes at a time
 
 // HALF: split BF16 form only, the unit offset of the low parts (kpad / 16).
 template <int PREC, int HALF = 0>
@@ -156,20 +174,31 @@ struct QEntry {
 // THR selects the threshold mode: the per-row threshold is fixed (the
 // requested one lowered by the row's rounding bound) and every value above it
 // is written straight to the row's candidate region; no lists are kept.
-template <int PREC, int UNITS, int TI, int C, bool THR = false>
+// SYM selects the symmetric form (Psi = Psi^T): workgroup b (rows of tiles
+// [16b, 16b + 16)) visits only column tiles >= 16b.  Inside its own block
+// both orientations are visited by its own waves; beyond it, each computed
+// value also serves row j of the column: it is kept for row j when it exceeds
+// tau[j], a bound under which no value of row j can matter (so the row side
+// of row j, which never visits columns of earlier blocks, misses nothing).
+// STRIDED visits every a.jt_stride-th column tile only (a sample of the columns).
+template <int PREC, int UNITS, int TI, int C, bool THR = false, bool SYM = false, bool STRIDED = false>
 __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   static_assert(TI == 1 || TI == 2, "one or two row tiles per wave");
   static_assert(!THR || TI == 2, "threshold mode keeps whole rows per lane");
+  static_assert(!SYM || (TI == 2 && !THR), "the symmetric form keeps whole rows per lane");
   constexpr bool PAIR = sweep_pairs(TI);
   constexpr int NSUB = sweep_nsub(TI);
   constexpr int TPS = sweep_tps(UNITS);
   constexpr int TILE_U = UNITS * 64;              // chunks per V tile
   constexpr int STAGE_U = TPS * TILE_U;           // chunks per stage
   constexpr int PF = (STAGE_U + SW_THREADS - 1) / SW_THREADS;
+  constexpr int TAU_N = SYM ? TPS * 32 : 4;       // column bounds of a stage's tiles
   // two stage buffers as distinct objects: LDS reads of one are then known not
   // to alias the global-to-LDS loads in flight into the other
   __shared__ u32x4 lds_a[STAGE_U];
   __shared__ u32x4 lds_b[STAGE_U];
+  __shared__ __attribute__((aligned(16))) float tau_a[TAU_N];
+  __shared__ __attribute__((aligned(16))) float tau_b[TAU_N];
   // queue[wave][entry][lane]: each lane appends to its own column
   __shared__ QEntry queue[SW_WAVES][SW_Q][64];
 
@@ -242,6 +271,23 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
       : 0.0;
   const float beta2 = (float)(2.0 * beta_own);
   float own_tau = -1.0f;   // max(lv[C-1], lv[k-1] - beta2), refreshed by flush
+  // symmetric form: the own row's list starts from its bound (none: -1)
+  float seed_own = -1.0f;
+  if constexpr (SYM) {
+    if (myrow_own >= 0 && myrow_own < n32) {
+      const float t = a.tau[myrow_own];
+      seed_own = t < INFINITY ? t : -1.0f;
+    }
+    own_tau = seed_own;
+    float x = own_tau, y = own_tau;
+    swap_halves(x, y);
+    tau[0] = x;
+    tau[TI - 1] = y;
+  }
+  // symmetric form: the wave's current pool chunk (-1: none yet, -2: the pool
+  // ran out) and the entries it holds
+  int cbase = -1;
+  int cused = 0;
   // the candidate region this lane writes in threshold mode
   const int to = PAIR ? h : 0;
   const int sub = PAIR ? 0 : h;
@@ -295,6 +341,7 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
 #pragma unroll
     for (int q = 1; q < C; ++q) kth = (q < a.k && lv[q] < kth) ? lv[q] : kth;
     own_tau = fmaxf(lv[C - 1], kth - beta2);
+    if constexpr (SYM) own_tau = fmaxf(own_tau, seed_own);
     if constexpr (PAIR) {
       float x = own_tau, y = own_tau;
       swap_halves(x, y);         // x: list of row l32 of tile 0, y: of tile 1
@@ -305,34 +352,68 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
     }
   };
 
-  const int jt0 = blockIdx.y * a.tiles_per_split;
-  const int jt1 = min(a.n_vtiles, jt0 + a.tiles_per_split);
-  const int nst = jt1 > jt0 ? (jt1 - jt0 + TPS - 1) / TPS : 0;
+  // column tiles: [jt0, jt1) every jstride-th (symmetric form: from the
+  // workgroup's first row tile on)
+  const int jstride = STRIDED && a.jt_stride > 1 ? a.jt_stride : 1;
+  const int jt0 = SYM ? (int)(a.row0 >> 5) + wg_t0 : blockIdx.y * a.tiles_per_split;
+  const int jt1 = SYM ? a.n_vtiles : min(a.n_vtiles, jt0 + a.tiles_per_split);
+  const int nl = jt1 > jt0 ? (jt1 - jt0 + jstride - 1) / jstride : 0;
+  const int nst = (nl + TPS - 1) / TPS;
+  // symmetric form: tiles from here on lie beyond the workgroup's own rows
+  const int own_end = (int)(a.row0 >> 5) + wg_t0 + SW_WAVES * TI;
 
   // Stage loads go straight from global memory into LDS (global_load_lds,
   // 16 bytes per lane): lane l of a wave writes slot (its wave's base) + l, so
   // chunk idx lands at lds[buf][idx].  Chunks past the column range are not
-  // loaded (their slots are never read).
-  auto load_stage = [&](int st, u32x4* dst) {
-    const int64_t base = (int64_t)(jt0 + st * TPS) * TILE_U;
-    const int64_t lim = (int64_t)jt1 * TILE_U;
+  // loaded (their slots are never read).  The symmetric form also stages the
+  // column bounds of the tiles (lanes 0 .. 8 TPS - 1 of wave 0, 16 bytes each).
+  auto load_stage = [&](int st, u32x4* dst, float* tdst) {
+    if constexpr (STRIDED) {
 #pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      const int idx = tid + q * SW_THREADS;
-      const int64_t g = base + idx;
-      if (idx < STAGE_U && g < lim)
-        __builtin_amdgcn_global_load_lds((const void*)(a.Vp + g),
-                                         (__attribute__((address_space(3))) void*)(dst + (idx & ~63)), 16, 0, 0);
+      for (int q = 0; q < PF; ++q) {
+        const int idx = tid + q * SW_THREADS;
+        const int tl = idx / TILE_U;
+        const int jl = st * TPS + tl;
+        if (idx < STAGE_U && jl < nl) {
+          const int64_t g = (int64_t)(jt0 + jl * jstride) * TILE_U + (idx - tl * TILE_U);
+          __builtin_amdgcn_global_load_lds((const void*)(a.Vp + g),
+                                           (__attribute__((address_space(3))) void*)(dst + (idx & ~63)), 16, 0, 0);
+        }
+      }
+    } else {
+      const int64_t base = (int64_t)(jt0 + st * TPS) * TILE_U;
+      const int64_t lim = (int64_t)jt1 * TILE_U;
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int idx = tid + q * SW_THREADS;
+        const int64_t g = base + idx;
+        if (idx < STAGE_U && g < lim)
+          __builtin_amdgcn_global_load_lds((const void*)(a.Vp + g),
+                                           (__attribute__((address_space(3))) void*)(dst + (idx & ~63)), 16, 0, 0);
+      }
+    }
+    if constexpr (SYM) {
+      // threads 0 .. 8 TPS - 1: the bounds, 16 bytes each (thread q lands at
+      // float 4q: its wave's base plus 16 bytes per lane)
+      static_assert(TPS * 8 <= SW_THREADS, "bound staging exceeds the workgroup");
+      if (tid < TPS * 8) {
+        const int jl = st * TPS + (tid >> 3);
+        if (jl < nl)
+          __builtin_amdgcn_global_load_lds((const void*)(a.tau + (int64_t)(jt0 + jl * jstride) * 32 + 4 * (tid & 7)),
+                                           (__attribute__((address_space(3))) void*)(tdst + 4 * (tid & ~63)), 16, 0,
+                                           0);
+      }
     }
   };
 
-  // the MFMA sweep of stage st, whose V tiles are in rd
-  auto sweep_stage = [&](int st, const u32x4* rd) {
+  // the MFMA sweep of stage st, whose V tiles are in rd (column bounds in trd)
+  auto sweep_stage = [&](int st, const u32x4* rd, const float* trd) {
     if (active) {
 #pragma unroll 1
       for (int tt = 0; tt < TPS; ++tt) {
-        const int jt = jt0 + st * TPS + tt;
-        if (jt >= jt1) break;
+        const int jl = st * TPS + tt;
+        if (jl >= nl) break;
+        const int jt = jt0 + jl * jstride;
         u32x4 av[UNITS];
 #pragma unroll
         for (int u = 0; u < UNITS; ++u) av[u] = rd[tt * TILE_U + u * 64 + lane];
@@ -393,6 +474,68 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
           if constexpr (PREC == P_FP8) thr[t] = __builtin_ldexpf(thr[t], -(ewt[t] + evt));
           pass[t] = mm > thr[t];
           any |= pass[t];
+        }
+        if constexpr (SYM) {
+          // column side (tiles beyond the workgroup's own rows, never masked):
+          // register v of this lane holds column j0 + acc_row(v, h) for the
+          // wave's rows l32 (tile 0) and 32 + l32 (tile 1); group g of half h
+          // is the four consecutive columns 8g + 4h .. 8g + 4h + 3
+          if (jt >= own_end) {
+            const float* tl = trd + tt * 32 + 4 * h;
+            bool cf = false;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              const float4 tg = *(const float4*)(tl + 8 * g);
+              cf |= fmaxf(fabsf(acc[0][4 * g]), fabsf(acc[TI - 1][4 * g])) > tg.x;
+              cf |= fmaxf(fabsf(acc[0][4 * g + 1]), fabsf(acc[TI - 1][4 * g + 1])) > tg.y;
+              cf |= fmaxf(fabsf(acc[0][4 * g + 2]), fabsf(acc[TI - 1][4 * g + 2])) > tg.z;
+              cf |= fmaxf(fabsf(acc[0][4 * g + 3]), fabsf(acc[TI - 1][4 * g + 3])) > tg.w;
+            }
+            if (__ballot(cf)) {
+#pragma unroll
+              for (int g = 0; g < 4; ++g) {
+                const float4 tg = *(const float4*)(tl + 8 * g);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  const int v = 4 * g + e;
+                  const float te = e == 0 ? tg.x : e == 1 ? tg.y : e == 2 ? tg.z : tg.w;
+#pragma unroll
+                  for (int t = 0; t < TI; ++t) {
+                    const float x = fabsf(acc[t][v]);
+                    const bool take = x > te && myrow[t] >= 0 && myrow[t] < n32;
+                    const unsigned long long mk = __ballot(take);
+                    if (mk) {
+                      const int m = (int)__popcll(mk);
+                      if (cbase == -1 || (cbase >= 0 && cused + m > CS_CHUNK)) {
+                        // close the chunk, take the next one from the pool
+                        if (cbase >= 0 && lane == 0) a.cs_fill[cbase / CS_CHUNK] = cused;
+                        unsigned got = 0;
+                        if (lane == 0) got = atomicAdd(a.cs_next, (unsigned)CS_CHUNK);
+                        got = (unsigned)__builtin_amdgcn_readfirstlane((int)got);
+                        if ((long long)got + CS_CHUNK > (long long)a.cs_cap) {
+                          if (lane == 0) atomicOr(a.cs_overflow, 1);
+                          cbase = -2;
+                        } else {
+                          cbase = (int)got;
+                        }
+                        cused = 0;
+                      }
+                      if (cbase >= 0) {
+                        const int pos = cbase + cused + (int)__builtin_amdgcn_mbcnt_hi(
+                                                (unsigned)(mk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+                        if (take) {
+                          a.cs_j[pos] = j0 + acc_row(v, h);
+                          a.cs_i[pos] = myrow[t];
+                          a.cs_v[pos] = x;
+                        }
+                        cused += m;
+                      }
+                    }
+                  }
+                }
+              }
+            }
+          }
         }
         if (__ballot(any)) {
           // own-row values: with two row tiles, exchange the accumulators' lane
@@ -499,24 +642,27 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
     }
   };
 
-  if (nst > 0) load_stage(0, lds_a);
+  if (nst > 0) load_stage(0, lds_a, tau_a);
   // every prologue load (the B operands, stage 0) has landed
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   // stages alternate between the buffers; the other buffer was last read in the
   // previous stage, which every wave has left at the barrier
   for (int st = 0; st < nst; st += 2) {
-    if (st + 1 < nst) load_stage(st + 1, lds_b);  // lands in LDS during the MFMAs
-    sweep_stage(st, lds_a);
+    if (st + 1 < nst) load_stage(st + 1, lds_b, tau_b);  // lands in LDS during the MFMAs
+    sweep_stage(st, lds_a, tau_a);
     __builtin_amdgcn_s_waitcnt(0);                // this wave's loads have landed
     __syncthreads();                              // and everyone's
     if (st + 1 >= nst) break;
-    if (st + 2 < nst) load_stage(st + 2, lds_a);
-    sweep_stage(st + 1, lds_b);
+    if (st + 2 < nst) load_stage(st + 2, lds_a, tau_a);
+    sweep_stage(st + 1, lds_b, tau_b);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
+  if constexpr (SYM) {
+    if (cbase >= 0 && lane == 0) a.cs_fill[cbase / CS_CHUNK] = cused;
+  }
   if (!active) return;
   if constexpr (THR) {
     if (slot[to] >= 0) a.tcount[((int64_t)slot[to] * a.S + blockIdx.y) * NSUB + sub] = tcnt;
@@ -553,5 +699,7 @@ SweepFn pick_sweep_fp8_c16(int kpad);
 SweepFn pick_sweep_fp8_c32(int kpad);
 SweepFn pick_sweep_bf16x3(int kpad, int C);   // split BF16 re-sweep
 SweepFn pick_sweep_thr(int prec, int kpad);   // threshold mode
+SweepFn pick_sweep_bf16_sym(int kpad, int C); // symmetric form
+SweepFn pick_sweep_bf16_sample(int kpad, int C);   // every SweepArgs::jt_stride-th column tile
 
 }  // namespace gmgm_rc
