@@ -50,7 +50,7 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
 # sweep's sources it was taken on; when the sources differ the figure no longer
 # describes the kernel and traffic is reported as null.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "recompose_bf16_1M_r100_k10_hbm_counters.md")
-SWEEP_SOURCES = ["recompose_sweep.h", "sweep_bf16_c32.hip", "mfma_util.h", "recompose.hip"]
+SWEEP_SOURCES = ["recompose_sweep.h", "sweep_bf16_c32.hip", "sweep_bf16_sym.hip", "mfma_util.h", "recompose.hip"]
 
 
 def sweep_sources_sha256():
@@ -548,7 +548,12 @@ def main():
                 torch.empty(n * k, dtype=torch.int32, device="cuda"),
                 torch.empty(n * k, dtype=torch.float32, device="cuda"))
 
-    def run(prec, steps, warmup, out):
+    def run(prec, steps, warmup, out, form=None):
+        # form: "full" or "symmetric" forces the library's choice (None: its size rule)
+        if form is None:
+            os.environ.pop("GMGM_RECOMPOSE_PATH", None)
+        else:
+            os.environ["GMGM_RECOMPOSE_PATH"] = form
         for _ in range(warmup):
             g.recompose_topk(Vd, pd, k, prec=prec, out=out, check=False)
         g.sync()
@@ -564,6 +569,7 @@ def main():
         sweep_ms, cnt = g.kernel_times()
         g.sync()
         st = g.recompose_topk(Vd, pd, k, prec=prec, out=out, stats=True).stats
+        os.environ.pop("GMGM_RECOMPOSE_PATH", None)
         return dt / steps, sweep_ms / max(cnt, 1), st
 
     out_main = alloc()
@@ -572,6 +578,9 @@ def main():
     log(f"{args.prec}: {step_s * 1e3:.2f} ms/step, sweep {sweep_ms:.2f} ms, stats {st_main}")
 
     flops = 2.0 * r * n * n
+    # the dominant kernel's algorithmic work: every pair (i, j) for the full
+    # sweep, each pair once (r n^2) for the symmetric form
+    kflops = r * float(n) * n if st_main["symmetric"] else flops
     traffic, traffic_note = profiled_sweep_traffic(args.prec, n, r, k, args.workload)
     result = {
         "metric": METRIC, "value": n / step_s, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
@@ -580,15 +589,29 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "n": n, "r": r, "k": k, "prec": args.prec, "global_batch": n, "seq_len": None,
                    "parallelism": "none (1 GPU)"},
-        "roofline": {"bound": "mfma", "kernel": "sweep_kernel",
-                     "achieved": flops / (sweep_ms * 1e-3) / 1e12, "peak": PEAK_TFLOPS[args.prec],
-                     "unit": "TFLOP/s", "frac": flops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
+        "roofline": {"bound": "mfma",
+                     "kernel": "sweep_kernel (symmetric form)" if st_main["symmetric"] else "sweep_kernel",
+                     "achieved": kflops / (sweep_ms * 1e-3) / 1e12, "peak": PEAK_TFLOPS[args.prec],
+                     "unit": "TFLOP/s", "frac": kflops / (sweep_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
                      "traffic": traffic, "traffic_unit": "bytes", "traffic_source": traffic_note,
                      "sweep_ms": sweep_ms,
-                     "algorithmic_flops_per_launch": flops, "executed_mfma_flops": st_main["mfma_flops"]},
+                     "algorithmic_flops_per_launch": kflops,
+                     "executed_mfma_flops_per_step": st_main["mfma_flops"]},
         "stats": st_main,
     }
     ref = out_main
+    if st_main["symmetric"]:
+        # the full sweep on the same input, for comparison (same output required)
+        out = alloc()
+        log(f"timing {args.prec} full sweep: {args.compare_steps + 1} steps")
+        s, sw, st = run(args.prec, args.compare_steps + 1, 1, out, form="full")
+        same = bool(torch.equal(out[1], ref[1]) and torch.equal(out[2], ref[2]))
+        result["full_sweep"] = {"rows_per_s": n / s, "ms_per_step": s * 1e3, "sweep_ms": sw,
+                                "sweep_tflops": flops / (sw * 1e-3) / 1e12,
+                                "sweep_frac_of_peak": flops / (sw * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
+                                "stats": st, "same_csr_as_symmetric": same}
+        log(f"{args.prec} full sweep: {s * 1e3:.2f} ms/step, sweep {sw:.2f} ms, same CSR {same}")
+        del out
     for prec in [p for p in args.compare.split(",") if p in PEAK_TFLOPS and p != args.prec]:
         out = alloc()
         log(f"timing {prec}: {args.compare_steps} steps")

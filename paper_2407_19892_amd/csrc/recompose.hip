@@ -945,6 +945,61 @@ __global__ void __launch_bounds__(256) tau_kernel(const float* __restrict__ cval
   if (lane == 0) tau[i] = out;
 }
 
+// Exclusive prefix sum of per-row counts into int64 offsets (off[n] = total),
+// in three steps: sums of 1024-row blocks, their scan (one workgroup), then
+// each block's own scan plus its base.
+__device__ inline long long block_scan_1024(long long v, long long* sh, long long* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {   // inclusive scan (Hillis-Steele)
+    const long long w = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += w;
+    __syncthreads();
+  }
+  *total = sh[1023];
+  const long long ex = t > 0 ? sh[t - 1] : 0;
+  __syncthreads();
+  return ex;
+}
+
+__global__ void __launch_bounds__(1024) rows_block_sum_kernel(const int* __restrict__ cnt, int64_t n,
+                                                              long long* __restrict__ bsum) {
+  __shared__ long long sh[1024];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  long long tot;
+  block_scan_1024(i < n ? cnt[i] : 0, sh, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) rows_base_scan_kernel(long long* __restrict__ bsum, int nb,
+                                                              int64_t* __restrict__ off_end, long long* __restrict__ info) {
+  __shared__ long long sh[1024];
+  long long run = 0;
+  for (int b0 = 0; b0 < nb; b0 += 1024) {
+    const int b = b0 + threadIdx.x;
+    long long tot;
+    const long long ex = block_scan_1024(b < nb ? bsum[b] : 0, sh, &tot);
+    if (b < nb) bsum[b] = run + ex;
+    run += tot;
+  }
+  if (threadIdx.x == 0) {
+    *off_end = run;
+    info[0] = run;
+  }
+}
+
+__global__ void __launch_bounds__(1024) rows_offsets_kernel(const int* __restrict__ cnt, int64_t n,
+                                                            const long long* __restrict__ bbase,
+                                                            int64_t* __restrict__ off) {
+  __shared__ long long sh[1024];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  long long tot;
+  const long long ex = block_scan_1024(i < n ? cnt[i] : 0, sh, &tot);
+  if (i < n) off[i] = bbase[blockIdx.x] + ex;
+}
+
 // Column-side entries per row: count (one workgroup per pool chunk; chunks
 // never handed out have fill 0).
 __global__ void __launch_bounds__(256) cs_count_kernel(const int* __restrict__ cs_j, const int* __restrict__ fill,
@@ -1159,11 +1214,13 @@ extern "C" gmgm_status gmgm_recompose_topk_noalloc(gmgm_ctx_t c, int64_t n, int6
   return s;
 }
 
-// The symmetric form serves BF16 calls for every row (n >= 1024, outside
-// allocation-free calls) when GMGM_RECOMPOSE_PATH=symmetric.  It is not the
-// default: at n = 1M, r = 100, k = 10 it executes 0.61 of the full sweep's
-// MFMA work but takes longer, the column-side test and appends costing more
-// than the tiles it skips.
+// The symmetric form serves BF16 calls for every row of Psi (outside
+// allocation-free calls) from SYM_MIN_N rows on; GMGM_RECOMPOSE_PATH=full or
+// =symmetric (n >= 1024) overrides the size rule.  Measured with r = 100,
+// k = 10 on clustered factors: 0.92x the full sweep's step time at n = 10^6,
+// 1.08x at n = 2^19 (its bound pass and grouping cost a fixed share that the
+// halved sweep outgrows only at large n).
+constexpr int64_t SYM_MIN_N = 800000;
 constexpr int SYM_STRIDE = 8;         // the bound pass visits every 8th column tile
 // Column-side pool: SYM_MARGIN times the entries expected (a value beats its
 // row's bound with probability about k SYM_STRIDE / n, the bound being near
@@ -1173,7 +1230,9 @@ constexpr double SYM_MARGIN = 4.0;
 static bool sym_wanted(gmgm_ctx* c, int prec, int64_t n, int64_t row_begin, int64_t row_end) {
   if (prec != P_BF16 || row_begin != 0 || row_end != n || c->arena || n < 1024) return false;
   const char* e = getenv("GMGM_RECOMPOSE_PATH");
-  return e && !strcmp(e, "symmetric");
+  if (e && !strcmp(e, "full")) return false;
+  if (e && !strcmp(e, "symmetric")) return true;
+  return n >= SYM_MIN_N;
 }
 
 struct SymBufs {
@@ -1223,7 +1282,8 @@ static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, c
   const size_t o_ai = o_av + up((size_t)w_rows * CA * 4);
   const size_t o_cnt = o_ai + up((size_t)w_rows * CA * 4);
   const size_t o_off = o_cnt + up((size_t)n * 4);
-  const size_t o_info = o_off + up((size_t)(n + 1) * 8);
+  const size_t o_bs = o_off + up((size_t)(n + 1) * 8);
+  const size_t o_info = o_bs + up((size_t)ceil_div(n, 1024) * 8);
   const size_t o_flag = o_info + 256;
   const size_t o_fill = o_flag + 256;
   const size_t bytes0 = o_fill + up((size_t)chunks * 4);
@@ -1236,6 +1296,7 @@ static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, c
   int* ai = (int*)(b0 + o_ai);
   int* per_row = (int*)(b0 + o_cnt);
   int64_t* off = (int64_t*)(b0 + o_off);
+  long long* bsum = (long long*)(b0 + o_bs);
   long long* info = (long long*)(b0 + o_info);
   unsigned* next = (unsigned*)(b0 + o_flag);
   int* flag = (int*)(b0 + o_flag + 8);
@@ -1276,11 +1337,15 @@ static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, c
                      (int)n);
   hipLaunchKernelGGL(cs_count_kernel, dim3((unsigned)chunks), dim3(256), 0, st, (const int*)cs_j,
                      (const int*)fill, n, per_row);
-  hipLaunchKernelGGL(thr_scan_kernel, dim3(1), dim3(1024), 0, st, (const int*)per_row, n, off, info);
+  const int nb = (int)ceil_div(n, 1024);
+  hipLaunchKernelGGL(rows_block_sum_kernel, dim3((unsigned)nb), dim3(1024), 0, st, (const int*)per_row, n, bsum);
+  hipLaunchKernelGGL(rows_base_scan_kernel, dim3(1), dim3(1024), 0, st, bsum, nb, off + n, info);
+  hipLaunchKernelGGL(rows_offsets_kernel, dim3((unsigned)nb), dim3(1024), 0, st, (const int*)per_row, n,
+                     (const long long*)bsum, off);
   GMGM_HIP(c, hipGetLastError());
-  long long h[2];
+  long long h[1];
   int hf = 0;
-  GMGM_HIP(c, hipMemcpyAsync(h, info, 16, hipMemcpyDeviceToHost, st));
+  GMGM_HIP(c, hipMemcpyAsync(h, info, 8, hipMemcpyDeviceToHost, st));
   GMGM_HIP(c, hipMemcpyAsync(&hf, flag, 4, hipMemcpyDeviceToHost, st));
   GMGM_HIP(c, hipStreamSynchronize(st));
   // executed MFMA work: the bound pass over its tiles, the symmetric sweep

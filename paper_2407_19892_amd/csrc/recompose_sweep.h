@@ -175,7 +175,9 @@ struct QEntry {
 // requested one lowered by the row's rounding bound) and every value above it
 // is written straight to the row's candidate region; no lists are kept.
 // SYM selects the symmetric form (Psi = Psi^T): workgroup b (rows of tiles
-// [16b, 16b + 16)) visits only column tiles >= 16b.  Inside its own block
+// [16b, 16b + 16)) visits only column tiles >= 16b, from the last one down
+// (so the workgroups running together stream the same tiles, as in the full
+// sweep, and share them in L2).  Inside its own block
 // both orientations are visited by its own waves; beyond it, each computed
 // value also serves row j of the column: it is kept for row j when it exceeds
 // tau[j], a bound under which no value of row j can matter (so the row side
@@ -381,8 +383,15 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
         }
       }
     } else {
-      const int64_t base = (int64_t)(jt0 + st * TPS) * TILE_U;
-      const int64_t lim = (int64_t)jt1 * TILE_U;
+      int64_t base, lim;
+      if constexpr (SYM) {   // stages from the last column tile down
+        const int hi = jt1 - st * TPS;
+        base = (int64_t)max(jt0, hi - TPS) * TILE_U;
+        lim = (int64_t)hi * TILE_U;
+      } else {
+        base = (int64_t)(jt0 + st * TPS) * TILE_U;
+        lim = (int64_t)jt1 * TILE_U;
+      }
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
         const int idx = tid + q * SW_THREADS;
@@ -397,9 +406,10 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
       // float 4q: its wave's base plus 16 bytes per lane)
       static_assert(TPS * 8 <= SW_THREADS, "bound staging exceeds the workgroup");
       if (tid < TPS * 8) {
-        const int jl = st * TPS + (tid >> 3);
-        if (jl < nl)
-          __builtin_amdgcn_global_load_lds((const void*)(a.tau + (int64_t)(jt0 + jl * jstride) * 32 + 4 * (tid & 7)),
+        const int hi = jt1 - st * TPS;
+        const int jt = max(jt0, hi - TPS) + (tid >> 3);
+        if (jt < hi)
+          __builtin_amdgcn_global_load_lds((const void*)(a.tau + (int64_t)jt * 32 + 4 * (tid & 7)),
                                            (__attribute__((address_space(3))) void*)(tdst + 4 * (tid & ~63)), 16, 0,
                                            0);
       }
@@ -411,9 +421,16 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
     if (active) {
 #pragma unroll 1
       for (int tt = 0; tt < TPS; ++tt) {
-        const int jl = st * TPS + tt;
-        if (jl >= nl) break;
-        const int jt = jt0 + jl * jstride;
+        int jt;
+        if constexpr (SYM) {
+          const int hi = jt1 - st * TPS;
+          jt = max(jt0, hi - TPS) + tt;
+          if (jt >= hi) break;
+        } else {
+          const int jl = st * TPS + tt;
+          if (jl >= nl) break;
+          jt = jt0 + jl * jstride;
+        }
         u32x4 av[UNITS];
 #pragma unroll
         for (int u = 0; u < UNITS; ++u) av[u] = rd[tt * TILE_U + u * 64 + lane];
@@ -482,18 +499,19 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
           // is the four consecutive columns 8g + 4h .. 8g + 4h + 3
           if (jt >= own_end) {
             const float* tl = trd + tt * 32 + 4 * h;
-            bool cf = false;
+            bool cg[4];   // some value of group g (columns 8g + 4h ..) beats its column's bound
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
               const float4 tg = *(const float4*)(tl + 8 * g);
-              cf |= fmaxf(fabsf(acc[0][4 * g]), fabsf(acc[TI - 1][4 * g])) > tg.x;
-              cf |= fmaxf(fabsf(acc[0][4 * g + 1]), fabsf(acc[TI - 1][4 * g + 1])) > tg.y;
-              cf |= fmaxf(fabsf(acc[0][4 * g + 2]), fabsf(acc[TI - 1][4 * g + 2])) > tg.z;
-              cf |= fmaxf(fabsf(acc[0][4 * g + 3]), fabsf(acc[TI - 1][4 * g + 3])) > tg.w;
+              cg[g] = fmaxf(fabsf(acc[0][4 * g]), fabsf(acc[TI - 1][4 * g])) > tg.x;
+              cg[g] |= fmaxf(fabsf(acc[0][4 * g + 1]), fabsf(acc[TI - 1][4 * g + 1])) > tg.y;
+              cg[g] |= fmaxf(fabsf(acc[0][4 * g + 2]), fabsf(acc[TI - 1][4 * g + 2])) > tg.z;
+              cg[g] |= fmaxf(fabsf(acc[0][4 * g + 3]), fabsf(acc[TI - 1][4 * g + 3])) > tg.w;
             }
-            if (__ballot(cf)) {
+            if (__ballot(cg[0] || cg[1] || cg[2] || cg[3])) {
 #pragma unroll
               for (int g = 0; g < 4; ++g) {
+                if (!__ballot(cg[g])) continue;
                 const float4 tg = *(const float4*)(tl + 8 * g);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
