@@ -136,7 +136,9 @@ typedef struct {
  * every value of a computed tile above the bound of its column's row is kept
  * for that row too.  Same results, same certificate (a row also certifies
  * only when its bound plus margin is below its exact k-th value); when the
- * kept values outgrow their pool the call runs the full sweep instead
+ * kept values outgrow their pool (or one wave keeps more in one stage of a
+ * few column tiles than eight times the number expected) the call runs the
+ * full sweep instead
  * (stats->symmetric = 0).  At n = 10^6, r = 100, k = 10 it executes 0.61 of
  * the full sweep's MFMA work in 0.92 of its time; below about 8e5 rows its
  * bound pass and grouping cost more than the skipped tiles save.

@@ -1003,9 +1003,9 @@ __global__ void __launch_bounds__(1024) rows_offsets_kernel(const int* __restric
 // Column-side entries per row: count (one workgroup per pool chunk; chunks
 // never handed out have fill 0).
 __global__ void __launch_bounds__(256) cs_count_kernel(const int* __restrict__ cs_j, const int* __restrict__ fill,
-                                                       int64_t n, int* __restrict__ per_row) {
-  const int m = min(fill[blockIdx.x], CS_CHUNK);
-  const int64_t b = (int64_t)blockIdx.x * CS_CHUNK;
+                                                       int chunk, int64_t n, int* __restrict__ per_row) {
+  const int m = min(fill[blockIdx.x], chunk);
+  const int64_t b = (int64_t)blockIdx.x * chunk;
   for (int e = threadIdx.x; e < m; e += blockDim.x) {
     const int j = cs_j[b + e];
     if (j >= 0 && j < n) atomicAdd(&per_row[j], 1);
@@ -1016,11 +1016,11 @@ __global__ void __launch_bounds__(256) cs_count_kernel(const int* __restrict__ c
 // the order inside a run is arbitrary, the finalize orders by value and index).
 __global__ void __launch_bounds__(256) cs_scatter_kernel(const int* __restrict__ cs_j, const int* __restrict__ cs_i,
                                                          const float* __restrict__ cs_v, const int* __restrict__ fill,
-                                                         int64_t n, const int64_t* __restrict__ off,
+                                                         int chunk, int64_t n, const int64_t* __restrict__ off,
                                                          int* __restrict__ per_row, int* __restrict__ xidx,
                                                          float* __restrict__ xval) {
-  const int m = min(fill[blockIdx.x], CS_CHUNK);
-  const int64_t b = (int64_t)blockIdx.x * CS_CHUNK;
+  const int m = min(fill[blockIdx.x], chunk);
+  const int64_t b = (int64_t)blockIdx.x * chunk;
   for (int e = threadIdx.x; e < m; e += blockDim.x) {
     const int j = cs_j[b + e];
     if (j < 0 || j >= n) continue;
@@ -1224,7 +1224,9 @@ constexpr int64_t SYM_MIN_N = 800000;
 constexpr int SYM_STRIDE = 8;         // the bound pass visits every 8th column tile
 // Column-side pool: SYM_MARGIN times the entries expected (a value beats its
 // row's bound with probability about k SYM_STRIDE / n, the bound being near
-// the k-th largest of a 1/SYM_STRIDE sample), plus a chunk per wave.
+// the k-th largest of a 1/SYM_STRIDE sample), plus a chunk per wave.  A chunk
+// holds at least 2048 entries and twice SYM_MARGIN times what a wave expects
+// in one stage (a stage starts with half a chunk free).
 constexpr double SYM_MARGIN = 4.0;
 
 static bool sym_wanted(gmgm_ctx* c, int prec, int64_t n, int64_t row_begin, int64_t row_end) {
@@ -1251,7 +1253,9 @@ struct SymBufs {
 //     above tau[j] go to the column-side pool;
 //  3. the column-side entries grouped by row (count, prefix sum, scatter), for
 //     the finalize to take with the lists.
-// Sets *overflow (and does nothing else after step 2) when the pool ran out.
+// Sets *overflow (and does nothing else after step 2) when the pool ran out
+// or one wave's stage produced more entries than the half chunk it started
+// with.
 static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, const double* psi, int r, int kpad,
                              int C, int64_t gx, SymBufs* out, double* flops, bool* overflow) {
   hipStream_t st = c->stream;
@@ -1271,9 +1275,12 @@ static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, c
     const int64_t tb = std::max<int64_t>(0, n_vtiles - (b + 1) * SW_WAVES * 2);
     expect += SW_WAVES * 64.0 * 32.0 * (double)tb * p_hit;
   }
-  const int64_t chunks = (int64_t)std::ceil(SYM_MARGIN * expect / CS_CHUNK) + gx * SW_WAVES;
-  const int64_t cap = chunks * CS_CHUNK;
-  if (cap >= ((int64_t)1 << 31) - CS_CHUNK) return set_err(c, GMGM_E_SHAPE, "column-side pool too large");
+  const int tps = sweep_tps(kpad / 16);   // column tiles per stage (BF16 units of 16)
+  const double per_stage = 64.0 * 32.0 * tps * p_hit;
+  const int chunk = (int)std::max<double>(2048.0, std::ceil(2.0 * SYM_MARGIN * per_stage / 256.0) * 256.0);
+  const int64_t chunks = (int64_t)std::ceil(SYM_MARGIN * expect / chunk) + gx * SW_WAVES;
+  const int64_t cap = chunks * chunk;
+  if (cap >= ((int64_t)1 << 31) - chunk) return set_err(c, GMGM_E_SHAPE, "column-side pool too large");
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   // WS_SYM0: tau | bound-pass lists (values, indices) | per-row counts | row
   // offsets | info | pool counter + flag | chunk fills
@@ -1327,6 +1334,7 @@ static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, c
   sy.cs_v = cs_v;
   sy.cs_next = next;
   sy.cs_cap = (int)cap;
+  sy.cs_chunk = chunk;
   sy.cs_fill = fill;
   sy.cs_overflow = flag;
   hipEvent_t t0 = timing_start(c);
@@ -1336,7 +1344,7 @@ static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, c
   hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, (unsigned*)per_row,
                      (int)n);
   hipLaunchKernelGGL(cs_count_kernel, dim3((unsigned)chunks), dim3(256), 0, st, (const int*)cs_j,
-                     (const int*)fill, n, per_row);
+                     (const int*)fill, chunk, n, per_row);
   const int nb = (int)ceil_div(n, 1024);
   hipLaunchKernelGGL(rows_block_sum_kernel, dim3((unsigned)nb), dim3(1024), 0, st, (const int*)per_row, n, bsum);
   hipLaunchKernelGGL(rows_base_scan_kernel, dim3(1), dim3(1024), 0, st, bsum, nb, off + n, info);
@@ -1368,8 +1376,8 @@ static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, c
   int* xidx = (int*)w2;
   float* xval = (float*)(xidx + tot);
   hipLaunchKernelGGL(cs_scatter_kernel, dim3((unsigned)chunks), dim3(256), 0, st, (const int*)cs_j,
-                     (const int*)cs_i, (const float*)cs_v, (const int*)fill, n, (const int64_t*)off, per_row, xidx,
-                     xval);
+                     (const int*)cs_i, (const float*)cs_v, (const int*)fill, chunk, n, (const int64_t*)off, per_row,
+                     xidx, xval);
   GMGM_HIP(c, hipGetLastError());
   out->tau = tau;
   out->off = off;
@@ -1477,7 +1485,7 @@ static gmgm_status topk_impl(gmgm_ctx* c, int64_t n, int64_t r, const float* V, 
   if (sym) {
     bool overflow = false;
     GMGM_TRY(sym_sweep(c, sa, V, psi, (int)r, kpad, C, gx, &symb, &flops, &overflow));
-    if (overflow)   // the column side outgrew its pool: the full sweep instead
+    if (overflow)   // the column side outgrew its buffers: the full sweep instead
       return topk_impl(c, n, r, V, psi, row_begin, row_end, k, prec, C, smax, row_ptr_out, col_out, val_out,
                        stats, false);
   } else {

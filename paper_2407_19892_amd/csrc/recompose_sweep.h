@@ -68,19 +68,20 @@ struct SweepArgs {
   // j's final cut lowered by its rounding margin (+inf: none; padding +inf);
   // the row's own list starts from it, and values Psi_ij of the column side
   // above tau[j] go to a shared pool as (j, i, |Psi_ij|): a wave takes
-  // CS_CHUNK entries at a time (cs_next counts the entries handed out, up to
-  // cs_cap) and records how many of a chunk it filled in cs_fill[chunk]
+  // cs_chunk entries at a time, at the start of a stage whose chunk has less
+  // than half of them free (cs_next counts the entries handed out, up to
+  // cs_cap), and records how many of a chunk it filled in cs_fill[chunk]
   const float* tau;
   int* cs_j;
   int* cs_i;
   float* cs_v;
   unsigned* cs_next;
-  int cs_cap;             // below 2^31 - CS_CHUNK
+  int cs_cap;             // below 2^31 - cs_chunk
+  int cs_chunk;
   int* cs_fill;
   int* cs_overflow;       // set to 1 when the pool ran out (entries were lost)
 };
 
-constexpr int CS_CHUNK = 2048;   // column-side pool entries a wave takes at a time
 
 // HALF: split BF16 form only, the unit offset of the low parts (kpad / 16).
 template <int PREC, int HALF = 0>
@@ -418,6 +419,24 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
 
   // the MFMA sweep of stage st, whose V tiles are in rd (column bounds in trd)
   auto sweep_stage = [&](int st, const u32x4* rd, const float* trd) {
+    if constexpr (SYM) {
+      // a stage starts with at least half a chunk free in the wave's chunk
+      // (taking chunks here keeps the pool's returning atomic out of the tile
+      // loop, whose loads would otherwise wait for it)
+      if (active && cbase != -2 && (cbase == -1 || 2 * cused > a.cs_chunk)) {
+        if (cbase >= 0 && lane == 0) a.cs_fill[cbase / a.cs_chunk] = cused;
+        unsigned got = 0;
+        if (lane == 0) got = atomicAdd(a.cs_next, (unsigned)a.cs_chunk);
+        got = (unsigned)__builtin_amdgcn_readfirstlane((int)got);
+        if ((long long)got + a.cs_chunk > (long long)a.cs_cap) {
+          if (lane == 0) atomicOr(a.cs_overflow, 1);
+          cbase = -2;
+        } else {
+          cbase = (int)got;
+        }
+        cused = 0;
+      }
+    }
     if (active) {
 #pragma unroll 1
       for (int tt = 0; tt < TPS; ++tt) {
@@ -524,19 +543,11 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
                     const unsigned long long mk = __ballot(take);
                     if (mk) {
                       const int m = (int)__popcll(mk);
-                      if (cbase == -1 || (cbase >= 0 && cused + m > CS_CHUNK)) {
-                        // close the chunk, take the next one from the pool
-                        if (cbase >= 0 && lane == 0) a.cs_fill[cbase / CS_CHUNK] = cused;
-                        unsigned got = 0;
-                        if (lane == 0) got = atomicAdd(a.cs_next, (unsigned)CS_CHUNK);
-                        got = (unsigned)__builtin_amdgcn_readfirstlane((int)got);
-                        if ((long long)got + CS_CHUNK > (long long)a.cs_cap) {
-                          if (lane == 0) atomicOr(a.cs_overflow, 1);
-                          cbase = -2;
-                        } else {
-                          cbase = (int)got;
-                        }
-                        cused = 0;
+                      if (cbase >= 0 && cused + m > a.cs_chunk) {
+                        // more than the room the stage started with: the
+                        // call falls back to the full sweep
+                        if (lane == 0) atomicOr(a.cs_overflow, 1);
+                        cbase = -2;
                       }
                       if (cbase >= 0) {
                         const int pos = cbase + cused + (int)__builtin_amdgcn_mbcnt_hi(
@@ -679,7 +690,7 @@ __global__ void __launch_bounds__(SW_THREADS) sweep_kernel(SweepArgs a) {
   }
 
   if constexpr (SYM) {
-    if (cbase >= 0 && lane == 0) a.cs_fill[cbase / CS_CHUNK] = cused;
+    if (cbase >= 0 && lane == 0) a.cs_fill[cbase / a.cs_chunk] = cused;
   }
   if (!active) return;
   if constexpr (THR) {
