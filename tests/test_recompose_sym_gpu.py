@@ -140,3 +140,27 @@ def test_symmetric_aligned_rounding_rows(lib, k):
     assert list(col[A["tie_row"]]) == A["tie_cols"][:k]
     assert st["rows_fallback"] >= 2, st
     assert st["rows_exact"] >= 1, st
+
+
+def test_size_rule_and_the_calls_that_stay_full(lib):
+    """At 820,000 rows a BF16 call for every row takes the symmetric form by
+    default; a row range, and GMGM_RECOMPOSE_PATH=full, take the full sweep.
+    The rows they share are identical, and sampled rows match the oracle."""
+    n, r, k = 820_000, 64, 10
+    V = synth.cell_factor_proxy(n, r, 40, seed=41)
+    psi = _psi(r, 41)
+    os.environ.pop("GMGM_RECOMPOSE_PATH", None)
+    rp, col, val, st = _run(lib, V, psi, k, "bf16")
+    assert st["symmetric"], st
+    b, e = 409_600, 411_203
+    rpr, colr, valr, str_ = _run(lib, V, psi, k, "bf16", row_begin=b, row_end=e)
+    assert not str_["symmetric"], str_
+    assert np.array_equal(colr, col[b * k:e * k]) and np.array_equal(valr, val[b * k:e * k])
+    with _path("full"):
+        rpf, colf, valf, stf = _run(lib, V, psi, k, "bf16")
+    assert not stf["symmetric"], stf
+    assert np.array_equal(colf, col) and np.array_equal(valf, val)
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([np.arange(16), np.arange(n - 16, n), rng.choice(n, 120, replace=False)]))
+    sel = (rows[:, None] * k + np.arange(k)[None, :]).ravel()
+    _check(V, psi, k, rows, np.arange(rows.size + 1) * k, col[sel], val[sel], "size rule 820k sampled")
