@@ -164,3 +164,21 @@ def test_size_rule_and_the_calls_that_stay_full(lib):
     rows = np.unique(np.concatenate([np.arange(16), np.arange(n - 16, n), rng.choice(n, 120, replace=False)]))
     sel = (rows[:, None] * k + np.arange(k)[None, :]).ravel()
     _check(V, psi, k, rows, np.arange(rows.size + 1) * k, col[sel], val[sel], "size rule 820k sampled")
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_symmetric_nonfinite_input_reports_domain_error(lib, bad):
+    """A non-finite entry of V in the symmetric form: the call stays
+    memory-safe and reports E_DOMAIN, and the context stays usable."""
+    import torch
+    V = torch.from_numpy(synth.cell_factor_proxy(2048, 16, 6, seed=50)).cuda()
+    V[700, 3] = bad
+    psi = torch.ones(16, dtype=torch.float64, device="cuda")
+    with _path("symmetric"):
+        with pytest.raises(lib.GmgmError) as ei:
+            lib.recompose_topk(V, psi, 5, prec="bf16")
+        assert ei.value.status == 3
+        lib.sync()                                   # the fault is reported once
+        V[700, 3] = 0.5
+        out = lib.recompose_topk(V, psi, 5, prec="bf16", stats=True)
+    assert out.col.shape[0] == 2048 * 5 and out.stats["symmetric"]
