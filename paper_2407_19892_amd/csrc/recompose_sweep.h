@@ -79,7 +79,8 @@ struct SweepArgs {
   int cs_cap;             // below 2^31 - cs_chunk
   int cs_chunk;
   int* cs_fill;
-  int* cs_overflow;       // set to 1 when the pool ran out (entries were lost)
+  int* cs_overflow;       // set to 1 when entries were lost (the pool ran out, or a
+                          // stage outgrew the half chunk its wave started with)
 };
 
 
