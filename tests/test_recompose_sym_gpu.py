@@ -1,6 +1,7 @@
 """Parity of the symmetric form of gmgm_recompose_topk (BF16 operands, every
-row of Psi; selected with GMGM_RECOMPOSE_PATH=symmetric) with the CPU oracle
-and with the full sweep of the same library.
+row of Psi; taken from 800,000 rows on, or forced with
+GMGM_RECOMPOSE_PATH=symmetric) with the CPU oracle and with the full sweep of
+the same library.
 
 Bar: against the oracle as for the full sweep (index sets identical except on
 near-tie rows, values within 1e-5 relative of FP64); against the full sweep:
