@@ -1255,7 +1255,7 @@ struct SymBufs {
 //     the finalize to take with the lists.
 // Sets *overflow (and does nothing else after step 2) when the pool ran out
 // or one wave's stage produced more entries than the half chunk it started
-// with.
+// with; before step 1 when the pool would need 2^31 entries or more.
 static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, const double* psi, int r, int kpad,
                              int C, int64_t gx, SymBufs* out, double* flops, bool* overflow) {
   hipStream_t st = c->stream;
@@ -1280,7 +1280,10 @@ static gmgm_status sym_sweep(gmgm_ctx* c, const SweepArgs& sa, const float* V, c
   const int chunk = (int)std::max<double>(2048.0, std::ceil(2.0 * SYM_MARGIN * per_stage / 256.0) * 256.0);
   const int64_t chunks = (int64_t)std::ceil(SYM_MARGIN * expect / chunk) + gx * SW_WAVES;
   const int64_t cap = chunks * chunk;
-  if (cap >= ((int64_t)1 << 31) - chunk) return set_err(c, GMGM_E_SHAPE, "column-side pool too large");
+  if (cap >= ((int64_t)1 << 31) - chunk) {   // 32-bit pool indices: the full sweep instead
+    *overflow = true;
+    return GMGM_OK;
+  }
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   // WS_SYM0: tau | bound-pass lists (values, indices) | per-row counts | row
   // offsets | info | pool counter + flag | chunk fills
