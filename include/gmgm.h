@@ -130,18 +130,18 @@ typedef struct {
  * each pair once): a BF16 call for every row (row_begin = 0, row_end = n,
  * r <= 128, k <= 24) with n >= 800000 (or n >= 1024 and the environment
  * variable GMGM_RECOMPOSE_PATH=symmetric; =full turns it off) computes only
- * the 32 x 32 tiles on or above the diagonal band of 512-row blocks.  Each row's list then
- * starts from a bound taken from a sweep over every 8th column tile (the
- * exact k-th of that sample's top k, less the row's rounding margin), and
- * every value of a computed tile above the bound of its column's row is kept
- * for that row too.  Same results, same certificate (a row also certifies
- * only when its bound plus margin is below its exact k-th value); when the
- * kept values outgrow their pool (or one wave keeps more in one stage of a
- * few column tiles than eight times the number expected) the call runs the
- * full sweep instead
- * (stats->symmetric = 0).  At n = 10^6, r = 100, k = 10 it executes 0.61 of
- * the full sweep's MFMA work in 0.92 of its time; below about 8e5 rows its
- * bound pass and grouping cost more than the skipped tiles save.
+ * the 32 x 32 tiles on or above the diagonal band of 512-row blocks.  Each
+ * row's list then starts from a bound taken from a sweep over every 8th
+ * column tile (the exact k-th of that sample's top k, less the row's
+ * rounding margin), and every value of a computed tile above the bound of
+ * its column's row is kept for that row too.  Same results, same certificate
+ * (a row also certifies only when its bound plus margin is below its exact
+ * k-th value); when the kept values outgrow their pool (or one wave keeps
+ * more in one stage of a few column tiles than eight times the number
+ * expected) the call runs the full sweep instead (stats->symmetric = 0).
+ * At n = 10^6, r = 100, k = 10 it executes 0.60 of the full sweep's MFMA
+ * work in about 0.92 of its time; below about 8e5 rows its bound pass and
+ * grouping cost more than the skipped tiles save.
  * The call synchronises once after the first sweep (and once more when rows
  * need the re-sweep) to size the re-sweep of uncertified rows.  With
  * the contraction streamed, rows the FP32 sweep cannot certify get their
