@@ -183,3 +183,15 @@ def test_symmetric_nonfinite_input_reports_domain_error(lib, bad):
         V[700, 3] = 0.5
         out = lib.recompose_topk(V, psi, 5, prec="bf16", stats=True)
     assert out.col.shape[0] == 2048 * 5 and out.stats["symmetric"]
+
+
+@pytest.mark.parametrize("n,r,k", [(5000, 100, 10), (3001, 128, 15), (2500, 40, 1)])
+def test_symmetric_with_lists_of_16(lib, n, r, k):
+    """cand_cap = 16 (the shorter lists: more rows go to the re-sweep) in the
+    symmetric form: the same CSR as the full sweep and the oracle's top k."""
+    V = synth.cell_factor_proxy(n, r, 6, seed=60 + k)
+    psi = _psi(r, 60 + k)
+    (rp, col, val, st), (rpf, colf, valf, stf) = _both(lib, V, psi, k, cand_cap=16)
+    assert st["symmetric"] and not stf["symmetric"], (st, stf)
+    assert np.array_equal(col, colf) and np.array_equal(val, valf)
+    _check(V, psi, k, np.arange(n), rp, col, val, f"symmetric C=16 n={n} r={r} k={k}")
