@@ -8,9 +8,12 @@ k = 10), BF16-MFMA sweep with exact rescoring, against the FP32-MFMA sweep
 
 A step is one pass of the whole recomposition path for all n rows: psi
 folding, operand repacking, the MFMA sweep, exact rescoring, the exact
-fallback for uncertified rows and the CSR emit.  Inputs (V, psi) are resident
-in HBM before timing starts.  Prints ONE JSON line on stdout; progress goes
-to stderr.
+fallback for uncertified rows and the CSR emit.  At this size the library
+takes the symmetric form of the sweep (tiles on or above the diagonal band,
+a bound pass over a column sample, the column side grouped by row); the full
+sweep is timed beside it on the same input and must give the same CSR.
+Inputs (V, psi) are resident in HBM before timing starts.  Prints ONE JSON
+line on stdout; progress goes to stderr.
 
 The other steps of the path are timed once each at the same workload's shape
 (reported under "stages", not part of the metric) on the 1M x 20k workload's
@@ -45,7 +48,7 @@ WORKLOAD_TEXT = {
              "Marchenko-Pastur + spike spectrum",
 }
 PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
-# HBM traffic of the BF16 sweep kernel at this workload comes from the committed
+# HBM traffic of the dominant sweep kernel at this workload comes from the committed
 # rocprofv3 FETCH_SIZE / WRITE_SIZE summary, which records the SHA-256 of the
 # sweep's sources it was taken on; when the sources differ the figure no longer
 # describes the kernel and traffic is reported as null.
@@ -63,7 +66,8 @@ def sweep_sources_sha256():
 
 
 def profiled_sweep_traffic(prec, n, r, k, workload_name):
-    """(bytes per launch, note) of the BF16 sweep from the counter summary."""
+    """(bytes per launch, note) of the metric's dominant sweep kernel from the
+    counter summary."""
     if (prec, n, r, k) != ("bf16", 1_000_000, 100, 10) or not os.path.exists(TRAFFIC_PROFILE):
         return None, "no counter profile for this configuration"
     vals = {}
